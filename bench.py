@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Throughput of the D3Q19 MRT permeability step on one MI355X.
+
+A step is one pass of the whole hot path over the fluid nodes: pull gather
+with halfway bounce-back, MRT + Guo collision, store, and the FP64
+mean-velocity reduction that feeds k and the convergence test (one kernel
+launch per step).  Inputs are resident in HBM before timing starts.
+
+Default workload: the 512^3 Gaussian-random-field rock of porosity 0.20
+(correlation length 6 voxels, x-spanning cluster only), tau = 1, Set E
+Lambda = 3/16, g = 1e-6.  `value` is MFLUPS with FP32 deviation storage; the
+FP16 and BF16 storage paths and the discrete adjoint are timed on the same
+image and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MFLUPS & %HBM peak, D3Q19-MRT 512^3 pack: fp32 vs fp16-store vs adjoint"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per fluid-lattice update: 19 populations read + 19 written.
+ALG_BYTES = {"f32": 19 * 4 * 2, "f16": 19 * 2 * 2, "bf16": 19 * 2 * 2}
+# Index bytes per node the design adds: int32 [18] table, or one packed coordinate.
+INDEX_BYTES = {"table": 18 * 4, "bitmap": 4}
+# Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n.
+ADJ_ALG_BYTES = 3 * 19 * 4
+
+
+def kernel_source_hash() -> str:
+    p = os.path.join(ROOT, "paper_1902_11193_amd", "csrc", "lbm_kernels.hip")
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(workload: str, storage: str, index: str):
+    """HBM bytes per launch from committed rocprofv3 FETCH_SIZE/WRITE_SIZE counts,
+    if they were taken on the current kernel source."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    e = d.get(f"{workload}/{storage}/{index}")
+    if not e or e.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_steps(solver, steps, warmup):
+    import torch
+
+    solver.step(warmup)
+    solver.mean_velocity()          # flush and sync
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    solver.step(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def run_forward(P, mask, args, storage):
+    import torch
+
+    s = P.Solver(mask, args.tau, args.Lambda, "E", (args.g, 0.0, 0.0), storage, args.index)
+    ms, wall = time_steps(s, args.steps, args.warmup)
+    k = float(s.permeability()[0])
+    nf = s.n_fluid
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    mflups = nf / (ms * 1e-3) / 1e6
+    alg_gbs = ALG_BYTES[storage] * nf / (ms * 1e-3) / 1e9
+    des_gbs = (ALG_BYTES[storage] + INDEX_BYTES[args.index]) * nf / (ms * 1e-3) / 1e9
+    return dict(ms_per_step=ms, MFLUPS=mflups, GBps_algorithmic=alg_gbs, GBps_designed=des_gbs,
+                frac_hbm_algorithmic=alg_gbs / HBM_PEAK_GBS, k_after_timed=k,
+                steps_total=args.warmup + args.steps, wall_s=wall)
+
+
+def run_adjoint(P, mask, args):
+    import torch
+
+    s = P.Solver(mask, args.tau, args.Lambda, "E", (args.g, 0.0, 0.0), "f32", args.index)
+    N, K = args.adj_steps, args.adj_checkpoint
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.adjoint(N, K)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    nf = s.n_fluid
+    s.close()
+    del s, r
+    torch.cuda.empty_cache()
+    # node-steps of the whole adjoint: forward N, recompute ~N, reverse N-1
+    return dict(n_steps=N, checkpoint_every=K, seconds=t, node_steps_per_s=nf * N / t,
+                MFLUPS_equivalent=nf * N / t / 1e6)
+
+
+def cpu_baseline(mask_full, crop_n: int, steps: int):
+    import torch
+
+    import oracle as O
+    from lbm_inputs import crop
+
+    m = crop(mask_full, crop_n)
+    p = O.Problem(m, 1.0, 3 / 16, "E", (1e-6, 0.0, 0.0))
+    t = O.time_steps(p, steps)
+    return dict(value=p.nf * steps / t / 1e6, unit="MFLUPS", cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{steps} steps of the FP64 oracle on the {crop_n}^3 corner crop of the workload "
+                       f"({p.nf} fluid nodes), {t:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="grf_512")
+    ap.add_argument("--index", default="bitmap", choices=["bitmap", "table"])
+    ap.add_argument("--variants", default="f16,bf16,adjoint")
+    ap.add_argument("--tau", type=float, default=1.0)
+    ap.add_argument("--Lambda", type=float, default=3 / 16)
+    ap.add_argument("--g", type=float, default=None)
+    ap.add_argument("--adj-steps", type=int, default=100)
+    ap.add_argument("--adj-checkpoint", type=int, default=10)
+    ap.add_argument("--cpu-crop", type=int, default=96)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(the domain would split into x-slabs with halo exchange; not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1902_11193_amd as P
+    from lbm_inputs import WORKLOADS, workload, porosity
+
+    w = WORKLOADS[args.workload]
+    if args.g is None:
+        args.g = w["g"]
+    t0 = time.time()
+    mask = workload(args.workload)
+    gen_s = time.time() - t0
+    print(f"[bench] {args.workload}: generated in {gen_s:.1f}s, porosity {porosity(mask):.4f}", file=sys.stderr,
+          flush=True)
+    torch.cuda.set_device(0)
+
+    main_r = run_forward(P, mask, args, "f32")
+    print(f"[bench] f32 {main_r['MFLUPS']:.0f} MFLUPS {main_r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    variants = {}
+    for v in [x for x in args.variants.split(",") if x]:
+        if v in ("f16", "bf16"):
+            variants[f"{v}_store"] = run_forward(P, mask, args, v)
+            variants[f"{v}_store"]["k_rel_vs_f32"] = variants[f"{v}_store"]["k_after_timed"] / main_r["k_after_timed"] - 1
+        elif v == "adjoint":
+            variants["adjoint"] = run_adjoint(P, mask, args)
+        print(f"[bench] {v} done", file=sys.stderr, flush=True)
+
+    nf = int((mask == 0).sum())
+    alg_per_launch = ALG_BYTES["f32"] * nf
+    achieved = alg_per_launch / (main_r["ms_per_step"] * 1e-3) / 1e9
+    traffic = traffic_for(args.workload, "f32", args.index)
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=traffic, kernel="k_step<CodecF32, BitmapIdx>" if args.index == "bitmap"
+                    else "k_step<CodecF32, TableIdx>", algorithmic_bytes_per_launch=alg_per_launch)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(mask, args.cpu_crop, args.cpu_steps)
+    out = {
+        "metric": METRIC,
+        "value": main_r["MFLUPS"],
+        "unit": "MFLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": w["n"], "porosity": porosity(mask), "n_fluid": nf,
+                   "tau": args.tau, "Lambda": args.Lambda, "relaxation_set": "E", "g": args.g,
+                   "storage": "f32", "index": args.index, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "f32": main_r,
+        "variants": variants,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

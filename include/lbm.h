@@ -1,0 +1,196 @@
+/*
+ * liblbm -- D3Q19 multiple-relaxation-time lattice-Boltzmann permeability
+ * solver for segmented voxel images on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Rao & Schaefer, "Lattice Boltzmann Models for Micro-tomographic
+ * Pore-spaces" (arXiv:1902.11193).  One time step is the lattice Boltzmann
+ * equation (Sec. 2, Eq. LBE) with the MRT collision of Sec. 2.1.1
+ * (Eqs. MRT Collision, MRT Equi, MRT params), Guo body forcing
+ * (Eqs. MRT-LBE, Guo_Forcing), halfway bounce-back at solid voxels in a
+ * periodic box driven by a uniform body force (Sec. 2.2), and the Darcy
+ * permeability k_j = nu <u_j> / g_j (Sec. 3, Eq. perm_calc) with the
+ * steady-state test of Eq. convergence.
+ *
+ * Conventions shared by every call
+ *   - geometry: uint8 [nz][ny][nx], x fastest; 0 = fluid, any other value =
+ *     solid.  The box is periodic in all three axes.
+ *   - Only fluid voxels carry populations.  They are numbered 0..n_fluid-1 in
+ *     raster order (x fastest) of the voxel image: the "compacted fluid list".
+ *   - Velocity order i = 0..18 (pairs i, i+1 for odd i are opposite):
+ *       0:( 0, 0, 0)
+ *       1:( 1, 0, 0)  2:(-1, 0, 0)  3:( 0, 1, 0)  4:( 0,-1, 0)
+ *       5:( 0, 0, 1)  6:( 0, 0,-1)  7:( 1, 1, 0)  8:(-1,-1, 0)
+ *       9:( 1,-1, 0) 10:(-1, 1, 0) 11:( 1, 0, 1) 12:(-1, 0,-1)
+ *      13:( 1, 0,-1) 14:(-1, 0, 1) 15:( 0, 1, 1) 16:( 0,-1,-1)
+ *      17:( 0, 1,-1) 18:( 0,-1, 1)
+ *     with weights 1/3, 1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2); rho0 = 1.
+ *   - State: post-collision populations after the last step.  On the device
+ *     they are stored as deviations f_i - w_i rho0 in FP32, FP16 or BF16
+ *     (FP16 scaled by a power of two); collision arithmetic is FP32; the mean
+ *     velocity and mass are reduced in FP64.
+ *   - Step n = gather (pull stream with halfway bounce-back), then collide.
+ *     <u>_n is the volume average (sum over fluid / (nx ny nz)) of the
+ *     shifted velocity (sum_i f_i c_i + F/2) / rho0 of the populations
+ *     gathered at step n.  The state starts at rest, f_i = w_i rho0.
+ *   - Memory: the library allocates no device memory.  The caller passes a
+ *     device workspace (size from lbm_workspace_query) that must outlive the
+ *     context.  All device work is enqueued on the caller's HIP stream.
+ *   - Errors: every int-returning call returns LBM_OK (0) or a negative code;
+ *     lbm_last_error() gives a message (thread-local).  Arguments are checked
+ *     before any HIP call is made.
+ */
+#ifndef LIBLBM_H
+#define LIBLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* bad argument (dims, tau <= 1/2, non-finite, set, rates outside (0,2)) */
+#define LBM_ENOFLUID (-2)   /* the image has no fluid voxel */
+#define LBM_EWORKSPACE (-3) /* workspace missing, too small or misaligned (needs 256-byte alignment) */
+#define LBM_EHIP (-4)       /* a HIP runtime call failed; message has the HIP error string */
+#define LBM_ENAN (-5)       /* non-finite mean velocity or mass: the run diverged or overflowed */
+#define LBM_ERANGE (-6)     /* image too large for the chosen index layout */
+
+/* Relaxation-rate sets of Table 2 (Sec. 2.1.3). */
+#define LBM_SRT 0
+#define LBM_SET_A 1
+#define LBM_SET_B 2
+#define LBM_SET_C 3
+#define LBM_SET_D 4
+#define LBM_SET_E 5
+
+/* Storage type of the population deviations. */
+#define LBM_F32 0
+#define LBM_F16 1
+#define LBM_BF16 2
+
+/* Neighbour layout used by the gather.
+ * LBM_INDEX_TABLE:  int32 [18][n_pad] table of pull-source nodes (-1 = wall),
+ *                   72 bytes per fluid node.
+ * LBM_INDEX_BITMAP: one packed uint32 voxel coordinate per node plus a fluid
+ *                   bitmap of the image and per-64-voxel prefix counts; the
+ *                   source node of a link is found by a population count.
+ *                   4 bytes per node + 3 bits per voxel.  Needs
+ *                   ceil(log2 nx) + ceil(log2 ny) + ceil(log2 nz) <= 32. */
+#define LBM_INDEX_TABLE 0
+#define LBM_INDEX_BITMAP 1
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Host only.  The velocity order above: c[i][0..2] = (cx, cy, cz). */
+int lbm_velocities(int c[19][3]);
+
+/* Host only.  The 19 diagonal entries of the relaxation matrix S
+ * (Eq. MRT params) for a set of Table 2 at (tau, Lambda); Lambda is read only
+ * for LBM_SET_E (Eq. Magic param).  Moment order: rho, e, eps, jx, qx, jy,
+ * qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz.  Also returns
+ * d s / d tau and d s / d Lambda when the pointers are non-NULL. */
+int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
+              double ds_dtau[19], double ds_dLambda[19]);
+
+/* Host only.  Counts fluid voxels and the device workspace the context
+ * needs.  Fails with LBM_ENOFLUID / LBM_ERANGE / LBM_EINVAL as lbm_setup. */
+int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
+                        int index_kind, size_t* bytes, int64_t* n_fluid);
+
+/* Host only (no GPU needed).  The pull-source table of the compacted fluid
+ * list: table[(i-1) * n_fluid + n] = node at x_n - c_i (periodic), or -1 when
+ * that voxel is solid (halfway bounce-back), for i = 1..18.  `table` holds
+ * 18 * n_fluid int32 and is owned by the caller. */
+int lbm_neighbor_table(const uint8_t* geometry, int nx, int ny, int nz, int32_t* table,
+                       int64_t n_fluid);
+
+/* Builds the context: copies and compacts the geometry (borrowed for the
+ * call only), computes the rates, uploads the index to `workspace` and sets
+ * the state to rest.  g[3] is the body-force acceleration (lattice units);
+ * F = rho0 g acts on every fluid node.  `hip_stream` is a hipStream_t (NULL =
+ * the default stream).  Returns the context in *ctx (owned by the caller,
+ * freed with lbm_destroy).  Synchronises the stream before returning. */
+int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
+              double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
+              void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* Advances n >= 0 time steps (asynchronous on the context's stream). */
+int lbm_step(lbm_ctx* ctx, int n);
+
+/* Steps taken since setup (or since the last lbm_set_state). */
+int64_t lbm_steps_done(const lbm_ctx* ctx);
+
+/* Mean velocity <u>_n of the last step (FP64).  Synchronises the stream.
+ * LBM_ENAN if it is not finite.  Before the first step: zeros. */
+int lbm_mean_velocity(lbm_ctx* ctx, double u[3]);
+
+/* k_j = nu <u_j>_n / g_j with nu = (tau - 1/2)/3 (Eq. perm_calc); NaN where
+ * g_j == 0.  Synchronises the stream. */
+int lbm_permeability(lbm_ctx* ctx, double k[3]);
+
+/* Sum over fluid nodes of the density deviation rho - rho0 at the last step
+ * (FP64); exact mass conservation keeps it at rounding level. */
+int lbm_mass_deviation(lbm_ctx* ctx, double* dm);
+
+/* Per-step mean velocities of the last `count` steps (count <= 1024 and
+ * <= steps done), oldest first, into u[count][3] (host).  Synchronises. */
+int lbm_history(lbm_ctx* ctx, int count, double* u);
+
+/* Steps in chunks of `check_every` until the per-step relative change of
+ * k along the largest |g| component falls below eps (Eq. convergence) or
+ * max_steps have run.  *steps = steps taken in this call, k = last k,
+ * *converged = 1 when the test held at some step of the last chunk. */
+int lbm_run_to_steady(lbm_ctx* ctx, double eps, int check_every, int max_steps, int* steps,
+                      double k[3], int* converged);
+
+/* Host copies of the state: full populations f_i = w_i rho0 + deviation in
+ * FP64, layout [19][n_fluid] (host memory owned by the caller).
+ * lbm_set_state also resets the step count and the mean-velocity history.
+ * Synchronise the stream. */
+int lbm_get_state(lbm_ctx* ctx, double* f);
+int lbm_set_state(lbm_ctx* ctx, const double* f);
+
+/* Linear voxel id (x + nx (y + ny z)) of every fluid node, host int64 [n_fluid]. */
+int lbm_fluid_index(lbm_ctx* ctx, int64_t* voxel);
+
+/* Optional per-node body force: a device FP32 array [3][n_fluid] of
+ * accelerations owned by the caller, read by every later step (it must stay
+ * alive and unchanged until replaced).  NULL returns to the uniform g of
+ * lbm_setup.  k keeps dividing by the g of lbm_setup. */
+int lbm_set_force_field(lbm_ctx* ctx, const float* g_device);
+
+int64_t lbm_n_fluid(const lbm_ctx* ctx);
+
+/* FP16 storage keeps 2^e (f_i - w_i rho0); e defaults to
+ * round(-log2 max|g|) - 4.  May be changed at any time (the state is
+ * rescaled).  Ignored for FP32 / BF16 storage, where e = 0. */
+int lbm_set_storage_exponent(lbm_ctx* ctx, int e);
+
+/* Discrete adjoint (spec extension of the paper's method): exact
+ * derivatives of k_N (the permeability after N = n_steps steps from rest,
+ * along the largest |g| component) with respect to tau, Lambda and the
+ * per-node body-force acceleration, by reverse time stepping with
+ * two-level checkpointing: a snapshot every `checkpoint_every` steps, the
+ * steps of one segment recomputed and kept while it is reversed.
+ * Re-runs the forward from rest; the context's state afterwards is the
+ * state after n_steps steps.  Needs FP32 storage.
+ * Workspace: size from lbm_adjoint_workspace_query, device, caller-owned.
+ * dk_dg: device FP64 [3][n_fluid] (caller-owned), overwritten.
+ * dk_dLambda is 0 unless the set is LBM_SET_E. */
+int lbm_adjoint_workspace_query(lbm_ctx* ctx, int n_steps, int checkpoint_every, size_t* bytes);
+int lbm_adjoint(lbm_ctx* ctx, int n_steps, int checkpoint_every, void* workspace,
+                size_t workspace_bytes, double* k, double* dk_dtau, double* dk_dLambda,
+                double* dk_dg);
+
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBLBM_H */

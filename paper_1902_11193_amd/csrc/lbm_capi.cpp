@@ -1,0 +1,656 @@
+// C-ABI of liblbm (declarations and contracts in include/lbm.h).
+#include "../../include/lbm.h"
+
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbm_host.hpp"
+#include "lbm_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(LBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kRing = 1024;
+constexpr int kMaxGrid = 8192;
+constexpr double kW[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+
+double weight(int i) {
+    const int q = lbm::kC[i][0] * lbm::kC[i][0] + lbm::kC[i][1] * lbm::kC[i][1] +
+                  lbm::kC[i][2] * lbm::kC[i][2];
+    return kW[q];
+}
+
+size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Workspace layout (byte offsets, each 256-aligned).
+struct Layout {
+    size_t A, B, table, coords, rowbits, wordbase, partials, ring, total;
+};
+
+Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int ny, int nz) {
+    Layout L{};
+    size_t off = 0;
+    const size_t state = align256((size_t)19 * np * elem_size(storage));
+    L.A = off;
+    off += state;
+    L.B = off;
+    off += state;
+    if (index_kind == LBM_INDEX_TABLE) {
+        L.table = off;
+        off += align256((size_t)18 * np * 4);
+    } else {
+        const size_t words = (size_t)ny * nz * ((nx + 63) / 64);
+        L.coords = off;
+        off += align256((size_t)std::max<int64_t>(nf, 1) * 4);
+        L.rowbits = off;
+        off += align256(words * 8);
+        L.wordbase = off;
+        off += align256(words * 4);
+    }
+    L.partials = off;  // two buffers: steps alternate between them
+    off += 2 * align256((size_t)kMaxGrid * 4 * 8);
+    L.ring = off;
+    off += align256((size_t)kRing * 4 * 8);
+    L.total = off;
+    return L;
+}
+
+std::string check_common(const uint8_t* geom, int nx, int ny, int nz, int storage,
+                         int index_kind) {
+    if (!geom) return "geometry is NULL";
+    std::string e = lbm::check_dims(nx, ny, nz);
+    if (!e.empty()) return e;
+    if (storage < LBM_F32 || storage > LBM_BF16) return "storage must be LBM_F32, LBM_F16 or LBM_BF16";
+    if (index_kind != LBM_INDEX_TABLE && index_kind != LBM_INDEX_BITMAP)
+        return "index_kind must be LBM_INDEX_TABLE or LBM_INDEX_BITMAP";
+    return "";
+}
+
+// FP16 / BF16 host encoders (round to nearest even).
+uint16_t to_bf16(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+float from_bf16(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float v;
+    std::memcpy(&v, &u, 4);
+    return v;
+}
+
+}  // namespace
+
+struct lbm_ctx {
+    int nx, ny, nz;
+    int64_t nf, np;
+    double tau, Lambda;
+    int set;
+    double g[3];
+    int axis;
+    int storage, index_kind;
+    lbm::RateClasses rates, ds_dtau, ds_dLambda;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    Layout L;
+    void* cur;   // state after the last step
+    void* nxt;
+    lbm::IndexView idx;
+    int grid;
+    double* partials[2];
+    double* ring;
+    int64_t steps;
+    bool pending;  // the last step's partials are not yet reduced into the ring
+    const float* field;
+    int exponent;
+    std::vector<uint8_t> geom;
+};
+
+namespace {
+
+lbm::RatesF rates_f(const lbm::RateClasses& r) {
+    return lbm::RatesF{(float)r.s_e, (float)r.s_eps, (float)r.s_q,
+                       (float)r.s_nu, (float)r.s_pi, (float)r.s_m};
+}
+
+float scale_of(const lbm_ctx* c) { return std::ldexp(1.0f, c->exponent); }
+
+// One forward step from `src` to `dst` with partial sums into `partials`;
+// when prev_out is non-null the same launch reduces prev_partials into it.
+hipError_t step_raw(lbm_ctx* c, const void* src, void* dst, double* partials,
+                    const double* prev_partials = nullptr, double* prev_out = nullptr) {
+    lbm::StepLaunch a{};
+    a.storage = c->storage;
+    a.src = src;
+    a.dst = dst;
+    a.idx = c->idx;
+    a.nf = c->nf;
+    a.rates = rates_f(c->rates);
+    a.F[0] = (float)c->g[0];
+    a.F[1] = (float)c->g[1];
+    a.F[2] = (float)c->g[2];
+    a.field = c->field;
+    a.scale = scale_of(c);
+    a.inv_scale = 1.0f / a.scale;
+    a.grid = c->grid;
+    a.partials = partials;
+    a.prev_partials = prev_partials;
+    a.prev_out = prev_out;
+    return lbm::launch_step(a, c->stream);
+}
+
+double* slot(lbm_ctx* c, int64_t step_index) { return c->ring + (step_index % kRing) * 4; }
+
+// Step n (0-based) writes partials[n % 2]; its launch also reduces the
+// partials of step n-1 into the ring.
+int do_steps(lbm_ctx* c, int n) {
+    for (int k = 0; k < n; ++k) {
+        const int64_t t = c->steps;
+        const double* prev = c->pending ? c->partials[(t - 1) & 1] : nullptr;
+        double* prev_out = c->pending ? slot(c, t - 1) : nullptr;
+        HIP_TRY(step_raw(c, c->cur, c->nxt, c->partials[t & 1], prev, prev_out));
+        std::swap(c->cur, c->nxt);
+        ++c->steps;
+        c->pending = true;
+    }
+    return LBM_OK;
+}
+
+// Reduce the last step's partials if that has not happened yet.
+int flush(lbm_ctx* c) {
+    if (!c->pending) return LBM_OK;
+    HIP_TRY(lbm::launch_finalize(c->partials[(c->steps - 1) & 1], c->grid, slot(c, c->steps - 1),
+                                 c->stream));
+    c->pending = false;
+    return LBM_OK;
+}
+
+int read_slot(lbm_ctx* c, int64_t step_index, double out[4]) {
+    int rc = flush(c);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(out, c->ring + (step_index % kRing) * 4, 4 * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+double volume(const lbm_ctx* c) { return (double)c->nx * c->ny * c->nz; }
+double viscosity(const lbm_ctx* c) { return (c->tau - 0.5) / 3.0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_err.c_str(); }
+
+int lbm_velocities(int c[19][3]) {
+    if (!c) return fail(LBM_EINVAL, "c is NULL");
+    for (int i = 0; i < 19; ++i)
+        for (int a = 0; a < 3; ++a) c[i][a] = lbm::kC[i][a];
+    return LBM_OK;
+}
+
+int lbm_rates(int set, double tau, double Lambda, double s[19], double ds_dtau[19],
+              double ds_dLambda[19]) {
+    lbm::RateClasses r{}, dt{}, dl{};
+    std::string e = lbm::rates(set, tau, Lambda, &r, &dt, &dl);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    if (s) lbm::rates_to_moments(r, s);
+    if (ds_dtau) lbm::rates_to_moments(dt, ds_dtau);
+    if (ds_dLambda) lbm::rates_to_moments(dl, ds_dLambda);
+    return LBM_OK;
+}
+
+int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
+                        int index_kind, size_t* bytes, int64_t* n_fluid) {
+    std::string e = check_common(geometry, nx, ny, nz, storage, index_kind);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    const int64_t nf = lbm::count_fluid(geometry, nx, ny, nz);
+    if (n_fluid) *n_fluid = nf;
+    if (nf == 0) return fail(LBM_ENOFLUID, "the image has no fluid voxel");
+    if (nf >= ((int64_t)1 << 31) - 256) return fail(LBM_ERANGE, "more than 2^31 fluid nodes");
+    if (index_kind == LBM_INDEX_BITMAP && !lbm::coord_bits(nx, ny, nz).fits())
+        return fail(LBM_ERANGE, "packed voxel coordinates need more than 32 bits");
+    if (bytes) *bytes = layout(lbm::padded(nf), nf, storage, index_kind, nx, ny, nz).total;
+    return LBM_OK;
+}
+
+int lbm_neighbor_table(const uint8_t* geometry, int nx, int ny, int nz, int32_t* table,
+                       int64_t n_fluid) {
+    std::string e = check_common(geometry, nx, ny, nz, LBM_F32, LBM_INDEX_TABLE);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    if (!table) return fail(LBM_EINVAL, "table is NULL");
+    const int64_t nf = lbm::count_fluid(geometry, nx, ny, nz);
+    if (nf != n_fluid) return fail(LBM_EINVAL, "n_fluid does not match the image");
+    if (nf == 0) return fail(LBM_ENOFLUID, "the image has no fluid voxel");
+    lbm::build_table(geometry, nx, ny, nz, nf, nf, table);
+    return LBM_OK;
+}
+
+int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
+              double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
+              void* workspace, size_t workspace_bytes, void* hip_stream) {
+    if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    std::string e = check_common(geometry, nx, ny, nz, storage, index_kind);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    if (!g) return fail(LBM_EINVAL, "g is NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(g[a])) return fail(LBM_EINVAL, "g must be finite");
+    lbm::RateClasses r{}, dt{}, dl{};
+    e = lbm::rates(relaxation_set, tau, Lambda, &r, &dt, &dl);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    size_t need = 0;
+    int64_t nf = 0;
+    int rc = lbm_workspace_query(geometry, nx, ny, nz, storage, index_kind, &need, &nf);
+    if (rc != LBM_OK) return rc;
+    if (!workspace) return fail(LBM_EWORKSPACE, "workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (workspace_bytes < need)
+        return fail(LBM_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+
+    // ---- everything below may call HIP
+    auto* c = new lbm_ctx();
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->nf = nf;
+    c->np = lbm::padded(nf);
+    c->tau = tau;
+    c->Lambda = Lambda;
+    c->set = relaxation_set;
+    for (int a = 0; a < 3; ++a) c->g[a] = g[a];
+    c->axis = 0;
+    for (int a = 1; a < 3; ++a)
+        if (std::fabs(g[a]) > std::fabs(g[c->axis])) c->axis = a;
+    c->storage = storage;
+    c->index_kind = index_kind;
+    c->rates = r;
+    c->ds_dtau = dt;
+    c->ds_dLambda = dl;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char*>(workspace);
+    c->ws_bytes = workspace_bytes;
+    c->L = layout(c->np, nf, storage, index_kind, nx, ny, nz);
+    c->cur = c->ws + c->L.A;
+    c->nxt = c->ws + c->L.B;
+    c->partials[0] = reinterpret_cast<double*>(c->ws + c->L.partials);
+    c->partials[1] = c->partials[0] + align256((size_t)kMaxGrid * 4 * 8) / 8;
+    c->pending = false;
+    c->ring = reinterpret_cast<double*>(c->ws + c->L.ring);
+    c->steps = 0;
+    c->field = nullptr;
+    c->geom.assign(geometry, geometry + (size_t)nx * ny * nz);
+    double gmax = std::max({std::fabs(g[0]), std::fabs(g[1]), std::fabs(g[2])});
+    c->exponent = (storage == LBM_F16 && gmax > 0) ? (int)std::lround(-std::log2(gmax)) - 4 : 0;
+    if (c->exponent < 0) c->exponent = 0;
+
+    int dev = 0, cus = 0;
+    auto cleanup = [&](int code) {
+        delete c;
+        return code;
+    };
+    hipError_t he = hipGetDevice(&dev);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("device query: ") + hipGetErrorString(he)));
+    const int64_t chunks = (nf + 255) / 256;
+    int64_t G = std::min<int64_t>(chunks, (int64_t)std::max(cus, 1) * 8);
+    if (G >= 64) G -= G % 8;
+    c->grid = (int)std::min<int64_t>(G, kMaxGrid);
+
+    lbm::IndexView& v = c->idx;
+    v.kind = index_kind;
+    v.stride = c->np;
+    std::vector<int32_t> table;
+    lbm::BitmapIndex bm;
+    if (index_kind == LBM_INDEX_TABLE) {
+        table.assign((size_t)18 * c->np, -1);
+        lbm::build_table(geometry, nx, ny, nz, nf, c->np, table.data());
+        v.table = reinterpret_cast<const int32_t*>(c->ws + c->L.table);
+        he = hipMemcpyAsync(c->ws + c->L.table, table.data(), table.size() * 4,
+                            hipMemcpyHostToDevice, c->stream);
+    } else {
+        lbm::build_bitmap(geometry, nx, ny, nz, nf, &bm);
+        v.coords = reinterpret_cast<const uint32_t*>(c->ws + c->L.coords);
+        v.rowbits = reinterpret_cast<const uint64_t*>(c->ws + c->L.rowbits);
+        v.wordbase = reinterpret_cast<const int32_t*>(c->ws + c->L.wordbase);
+        v.nx = nx;
+        v.ny = ny;
+        v.nz = nz;
+        v.W = bm.words_per_row;
+        v.bx = bm.bits.bx;
+        v.by = bm.bits.by;
+        he = hipMemcpyAsync(c->ws + c->L.coords, bm.coords.data(), bm.coords.size() * 4,
+                            hipMemcpyHostToDevice, c->stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(c->ws + c->L.rowbits, bm.rowbits.data(), bm.rowbits.size() * 8,
+                                hipMemcpyHostToDevice, c->stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(c->ws + c->L.wordbase, bm.wordbase.data(), bm.wordbase.size() * 4,
+                                hipMemcpyHostToDevice, c->stream);
+    }
+    if (he == hipSuccess) he = lbm::launch_zero(c->ws + c->L.A, (int64_t)(c->L.B - c->L.A) * 2, c->stream);
+    if (he == hipSuccess) he = lbm::launch_zero(c->ws + c->L.ring, (int64_t)kRing * 4 * 8, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("setup upload: ") + hipGetErrorString(he)));
+    *ctx = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx* c, int n) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    return do_steps(c, n);
+}
+
+int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->steps : -1; }
+int64_t lbm_n_fluid(const lbm_ctx* c) { return c ? c->nf : -1; }
+
+int lbm_mean_velocity(lbm_ctx* c, double u[3]) {
+    if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
+    if (c->steps == 0) {
+        u[0] = u[1] = u[2] = 0.0;
+        return LBM_OK;
+    }
+    double s[4];
+    int rc = read_slot(c, c->steps - 1, s);
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a) u[a] = s[a] / volume(c);
+    if (!std::isfinite(u[0]) || !std::isfinite(u[1]) || !std::isfinite(u[2]) || !std::isfinite(s[3]))
+        return fail(LBM_ENAN, "mean velocity or mass is not finite");
+    return LBM_OK;
+}
+
+int lbm_permeability(lbm_ctx* c, double k[3]) {
+    if (!c || !k) return fail(LBM_EINVAL, "NULL argument");
+    double u[3];
+    int rc = lbm_mean_velocity(c, u);
+    if (rc) return rc;
+    for (int a = 0; a < 3; ++a) k[a] = c->g[a] != 0 ? viscosity(c) * u[a] / c->g[a] : NAN;
+    return LBM_OK;
+}
+
+int lbm_mass_deviation(lbm_ctx* c, double* dm) {
+    if (!c || !dm) return fail(LBM_EINVAL, "NULL argument");
+    if (c->steps == 0) {
+        *dm = 0.0;
+        return LBM_OK;
+    }
+    double s[4];
+    int rc = read_slot(c, c->steps - 1, s);
+    if (rc) return rc;
+    *dm = s[3];
+    if (!std::isfinite(*dm)) return fail(LBM_ENAN, "mass is not finite");
+    return LBM_OK;
+}
+
+int lbm_history(lbm_ctx* c, int count, double* u) {
+    if (!c || !u) return fail(LBM_EINVAL, "NULL argument");
+    if (count < 0 || count > kRing || count > c->steps)
+        return fail(LBM_EINVAL, "count must be in [0, min(1024, steps done)]");
+    std::vector<double> ring((size_t)kRing * 4);
+    int rc = flush(c);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(ring.data(), c->ring, ring.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int t = 0; t < count; ++t) {
+        const int64_t step = c->steps - count + t;
+        for (int a = 0; a < 3; ++a) u[3 * t + a] = ring[(step % kRing) * 4 + a] / volume(c);
+    }
+    return LBM_OK;
+}
+
+int lbm_run_to_steady(lbm_ctx* c, double eps, int check_every, int max_steps, int* steps,
+                      double k[3], int* converged) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!(eps > 0) || check_every < 1 || check_every > kRing - 1 || max_steps < 0)
+        return fail(LBM_EINVAL, "need eps > 0, 1 <= check_every < 1024, max_steps >= 0");
+    if (c->g[c->axis] == 0) return fail(LBM_EINVAL, "no body force");
+    int done = 0, conv = 0;
+    std::vector<double> h;
+    while (done < max_steps && !conv) {
+        const int n = std::min(check_every, max_steps - done);
+        int rc = do_steps(c, n);
+        if (rc) return rc;
+        done += n;
+        const int m = (int)std::min<int64_t>(c->steps, n + 1);
+        h.assign((size_t)3 * m, 0.0);
+        rc = lbm_history(c, m, h.data());
+        if (rc) return rc;
+        for (int t = 1; t < m; ++t) {
+            const double a = h[3 * (t - 1) + c->axis], b = h[3 * t + c->axis];
+            if (!std::isfinite(b)) return fail(LBM_ENAN, "mean velocity is not finite");
+            if (c->steps - (m - 1 - t) >= 2 && std::fabs(b - a) < eps * std::fabs(b)) conv = 1;
+        }
+    }
+    if (steps) *steps = done;
+    if (converged) *converged = conv;
+    if (k) {
+        int rc = lbm_permeability(c, k);
+        if (rc) return rc;
+    }
+    return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* c, double* f) {
+    if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t es = elem_size(c->storage);
+    std::vector<char> raw((size_t)19 * c->np * es);
+    HIP_TRY(hipMemcpyAsync(raw.data(), c->cur, raw.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double inv = 1.0 / std::ldexp(1.0, c->exponent);
+    for (int i = 0; i < 19; ++i) {
+        const double w = weight(i);
+        for (int64_t n = 0; n < c->nf; ++n) {
+            const size_t at = (size_t)i * c->np + n;
+            double d;
+            if (c->storage == LBM_F32)
+                d = reinterpret_cast<const float*>(raw.data())[at];
+            else if (c->storage == LBM_F16)
+                d = (double)(float)reinterpret_cast<const _Float16*>(raw.data())[at] * inv;
+            else
+                d = (double)from_bf16(reinterpret_cast<const uint16_t*>(raw.data())[at]);
+            f[(size_t)i * c->nf + n] = w + d;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_set_state(lbm_ctx* c, const double* f) {
+    if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
+    const size_t es = elem_size(c->storage);
+    std::vector<char> raw((size_t)19 * c->np * es, 0);
+    const double sc = std::ldexp(1.0, c->exponent);
+    for (int i = 0; i < 19; ++i) {
+        const double w = weight(i);
+        for (int64_t n = 0; n < c->nf; ++n) {
+            const size_t at = (size_t)i * c->np + n;
+            const double d = f[(size_t)i * c->nf + n] - w;
+            if (c->storage == LBM_F32)
+                reinterpret_cast<float*>(raw.data())[at] = (float)d;
+            else if (c->storage == LBM_F16)
+                reinterpret_cast<_Float16*>(raw.data())[at] = (_Float16)(float)(d * sc);
+            else
+                reinterpret_cast<uint16_t*>(raw.data())[at] = to_bf16((float)d);
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(c->cur, raw.data(), raw.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(lbm::launch_zero(c->ring, (int64_t)kRing * 4 * 8, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->steps = 0;
+    c->pending = false;
+    return LBM_OK;
+}
+
+int lbm_fluid_index(lbm_ctx* c, int64_t* voxel) {
+    if (!c || !voxel) return fail(LBM_EINVAL, "NULL argument");
+    lbm::fluid_voxels(c->geom.data(), c->nx, c->ny, c->nz, voxel);
+    return LBM_OK;
+}
+
+int lbm_set_force_field(lbm_ctx* c, const float* g_device) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    c->field = g_device;
+    return LBM_OK;
+}
+
+int lbm_set_storage_exponent(lbm_ctx* c, int e) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->storage != LBM_F16) return LBM_OK;
+    if (e < -60 || e > 60) return fail(LBM_EINVAL, "exponent out of range [-60, 60]");
+    const float factor = std::ldexp(1.0f, e - c->exponent);
+    HIP_TRY(lbm::launch_rescale(c->storage, c->cur, (int64_t)19 * c->np, factor, c->stream));
+    c->exponent = e;
+    return LBM_OK;
+}
+
+// ---------------------------------------------------------------- adjoint
+namespace {
+struct AdjLayout {
+    size_t snaps, seg, adjA, adjB, part6, scratch4, out6, total;
+    int nsnap;
+};
+AdjLayout adj_layout(const lbm_ctx* c, int n_steps, int K) {
+    AdjLayout a{};
+    const size_t state = align256((size_t)19 * c->np * 4);
+    a.nsnap = std::max(1, (n_steps - 1 + K - 1) / K);
+    size_t off = 0;
+    a.snaps = off;
+    off += state * a.nsnap;
+    a.seg = off;
+    off += state * (size_t)std::max(K - 1, 0);
+    a.adjA = off;
+    off += state;
+    a.adjB = off;
+    off += state;
+    a.part6 = off;
+    off += align256((size_t)kMaxGrid * 6 * 8);
+    a.scratch4 = off;
+    off += align256((size_t)kMaxGrid * 4 * 8);
+    a.out6 = off;
+    off += 256;
+    a.total = off;
+    return a;
+}
+}  // namespace
+
+int lbm_adjoint_workspace_query(lbm_ctx* c, int n_steps, int K, size_t* bytes) {
+    if (!c || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    if (n_steps < 1 || K < 1) return fail(LBM_EINVAL, "need n_steps >= 1 and checkpoint_every >= 1");
+    *bytes = adj_layout(c, n_steps, K).total;
+    return LBM_OK;
+}
+
+int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_bytes, double* k_out,
+                double* dk_dtau, double* dk_dLambda, double* dk_dg) {
+    if (!c || !dk_dtau || !dk_dLambda || !dk_dg) return fail(LBM_EINVAL, "NULL argument");
+    if (c->storage != LBM_F32) return fail(LBM_EINVAL, "the adjoint needs FP32 storage");
+    if (N < 1 || K < 1) return fail(LBM_EINVAL, "need n_steps >= 1 and checkpoint_every >= 1");
+    if (c->g[c->axis] == 0) return fail(LBM_EINVAL, "no body force");
+    const AdjLayout A = adj_layout(c, N, K);
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(LBM_EWORKSPACE, "adjoint workspace NULL or not 256-byte aligned");
+    if (workspace_bytes < A.total)
+        return fail(LBM_EWORKSPACE, "adjoint workspace too small: need " + std::to_string(A.total));
+    char* ws = static_cast<char*>(workspace);
+    const size_t state = align256((size_t)19 * c->np * 4);
+    auto snap = [&](int s) { return (float*)(ws + A.snaps + state * s); };
+    auto seg = [&](int t) { return (float*)(ws + A.seg + state * (t - 1)); };  // t >= 1
+    double* part6 = (double*)(ws + A.part6);
+    double* scratch4 = (double*)(ws + A.scratch4);
+    double* out6 = (double*)(ws + A.out6);
+
+    // forward from rest to step N, keeping fh^{sK}
+    HIP_TRY(lbm::launch_zero(c->cur, (int64_t)19 * c->np * 4, c->stream));
+    HIP_TRY(lbm::launch_zero(c->ring, (int64_t)kRing * 4 * 8, c->stream));
+    c->steps = 0;
+    c->pending = false;
+    for (int n = 0; n < N; ++n) {
+        if (n % K == 0 && n / K < A.nsnap && n <= N - 1)
+            HIP_TRY(hipMemcpyAsync(snap(n / K), c->cur, (size_t)19 * c->np * 4,
+                                   hipMemcpyDeviceToDevice, c->stream));
+        int rc = do_steps(c, 1);
+        if (rc) return rc;
+    }
+    double u[3];
+    int rc = lbm_mean_velocity(c, u);
+    if (rc) return rc;
+    const double gref = c->g[c->axis], V = volume(c), nu = viscosity(c);
+    const double k = nu * u[c->axis] / gref;
+
+    // reverse sweep
+    float* a_in = (float*)(ws + A.adjA);
+    float* a_out = (float*)(ws + A.adjB);
+    HIP_TRY(lbm::launch_adjoint_seed(a_in, c->np, c->nf, c->axis, (float)(nu / (gref * V)), c->stream));
+    HIP_TRY(lbm::launch_zero(part6, (int64_t)kMaxGrid * 6 * 8, c->stream));
+    HIP_TRY(lbm::launch_zero(dk_dg, (int64_t)3 * c->nf * 8, c->stream));
+    lbm::AdjLaunch al{};
+    al.idx = c->idx;
+    al.nf = c->nf;
+    al.rates = rates_f(c->rates);
+    for (int a = 0; a < 3; ++a) al.F[a] = (float)c->g[a];
+    al.field = c->field;
+    al.dk_dF = dk_dg;
+    al.grid = c->grid;
+    al.partials = part6;
+    const int nrev = N - 1;  // reverse steps n = N-1 .. 1
+    for (int s = (nrev + K - 1) / K - 1; s >= 0; --s) {
+        const int n0 = s * K;                        // segment start: fh^{n0}
+        const int n1 = std::min((s + 1) * K, nrev);  // last reverse step of the segment
+        // recompute fh^{n0+1} .. fh^{n1-1}
+        for (int t = 1; t < n1 - n0; ++t) {
+            const void* src = t == 1 ? (const void*)snap(s) : (const void*)seg(t - 1);
+            HIP_TRY(step_raw(c, src, seg(t), scratch4));
+        }
+        for (int n = n1; n > n0; --n) {
+            al.adj_in = a_in;
+            al.adj_out = a_out;
+            al.state = (n - 1 - n0) == 0 ? snap(s) : seg(n - 1 - n0);
+            HIP_TRY(lbm::launch_adjoint_step(al, c->stream));
+            std::swap(a_in, a_out);
+        }
+    }
+    // readout's direct dependence on F through the shift u = (sum f c + F/2)
+    double dv[3] = {0, 0, 0};
+    dv[c->axis] = nu / (2.0 * gref * V);
+    HIP_TRY(lbm::launch_add_uniform(dk_dg, c->nf, dv[0], dv[1], dv[2], c->stream));
+    HIP_TRY(lbm::launch_finalize6(part6, c->grid, out6, c->stream));
+    double cls[6];
+    HIP_TRY(hipMemcpyAsync(cls, out6, sizeof(cls), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const lbm::RateClasses& dt = c->ds_dtau;
+    const lbm::RateClasses& dl = c->ds_dLambda;
+    const double via_t = cls[0] * dt.s_e + cls[1] * dt.s_eps + cls[2] * dt.s_q + cls[3] * dt.s_nu +
+                         cls[4] * dt.s_pi + cls[5] * dt.s_m;
+    const double via_l = cls[0] * dl.s_e + cls[1] * dl.s_eps + cls[2] * dl.s_q + cls[3] * dl.s_nu +
+                         cls[4] * dl.s_pi + cls[5] * dl.s_m;
+    *dk_dtau = via_t + u[c->axis] / (3.0 * gref);  // nu = (tau - 1/2)/3 in k
+    *dk_dLambda = c->set == LBM_SET_E ? via_l : 0.0;
+    if (k_out) *k_out = k;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+}  // extern "C"

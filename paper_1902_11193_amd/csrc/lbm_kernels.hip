@@ -1,0 +1,634 @@
+// gfx950 kernels of liblbm: one fused D3Q19 MRT stream-collide step over the
+// compacted fluid-node list, its discrete adjoint, and small helpers.
+//
+// Method: Rao & Schaefer, arXiv:1902.11193 -- lattice Boltzmann equation
+// (Sec. 2, Eq. LBE), MRT collision in moment space (Sec. 2.1.1, Eqs. MRT
+// Collision, MRT Equi, MRT params), Guo forcing (Eqs. MRT-LBE,
+// Guo_Forcing), halfway bounce-back and a periodic body-force-driven box
+// (Sec. 2.2), volume-averaged velocity for Darcy's law (Eq. perm_calc).
+//
+// Design for CDNA4: every fluid node is one lane of a wave64; populations are
+// structure-of-arrays [19][stride] so the 19 stores and the in-row gathers are
+// coalesced; the 19x19 transform M and its inverse M^T diag(1/|row|^2) are
+// written out as integer-coefficient adds on pair sums/differences of
+// opposite populations (no MFMA: at ~0.4 kflop per node-update against
+// ~150 bytes of traffic this is an HBM-bound stencil, not a contraction).
+// Storage holds deviations f_i - w_i rho0 (FP32, scaled FP16, BF16); all
+// arithmetic is FP32; the mean-velocity reduction is FP64 and deterministic
+// (fixed per-block node ranges, fixed reduction trees).
+#include "lbm_kernels.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+
+namespace lbm {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kXcds = 8;  // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+__host__ __device__ constexpr int cdir(int i, int a) {
+    constexpr int t[19][3] = {
+        {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+        {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+        {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+    return t[i][a];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+
+template <class F, int... I>
+__device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void unroll(F&& f) {
+    unroll_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ------------------------------------------------------------------ codecs
+struct CodecF32 {
+    using T = float;
+    static __device__ __forceinline__ float ld(const T* p, int64_t i, float) { return p[i]; }
+    static __device__ __forceinline__ void st(T* p, int64_t i, float v, float) { p[i] = v; }
+};
+struct CodecF16 {
+    using T = _Float16;
+    static __device__ __forceinline__ float ld(const T* p, int64_t i, float inv) {
+        return (float)p[i] * inv;
+    }
+    static __device__ __forceinline__ void st(T* p, int64_t i, float v, float s) {
+        p[i] = (_Float16)(v * s);
+    }
+};
+struct CodecBF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ float ld(const T* p, int64_t i, float inv) {
+        return __uint_as_float((uint32_t)p[i] << 16) * inv;
+    }
+    static __device__ __forceinline__ void st(T* p, int64_t i, float v, float s) {
+        const uint32_t u = __float_as_uint(v * s);
+        uint16_t r;
+        if ((u & 0x7fffffffu) > 0x7f800000u)
+            r = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+        else
+            r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // round to nearest even
+        p[i] = r;
+    }
+};
+
+// ------------------------------------------------------------------ indices
+struct TableIdx {
+    const int32_t* __restrict__ t;
+    int64_t stride;
+    struct Loc {};
+    __device__ __forceinline__ Loc locate(int64_t) const { return {}; }
+    // pull source of direction I at node n, -1 for a solid source
+    template <int I>
+    __device__ __forceinline__ int64_t src(const Loc&, int64_t n) const {
+        return t[(int64_t)(I - 1) * stride + n];
+    }
+};
+
+struct BitmapIdx {
+    const uint32_t* __restrict__ coords;
+    const uint64_t* __restrict__ rowbits;
+    const int32_t* __restrict__ wordbase;
+    int nx, ny, nz, W, bx, by;
+    struct Loc {
+        int x, y, z;
+    };
+    __device__ __forceinline__ Loc locate(int64_t n) const {
+        const uint32_t c = coords[n];
+        Loc l;
+        l.x = (int)(c & ((1u << bx) - 1u));
+        l.y = (int)((c >> bx) & ((1u << by) - 1u));
+        l.z = (int)((uint64_t)c >> (bx + by));
+        return l;
+    }
+    template <int I>
+    __device__ __forceinline__ int64_t src(const Loc& l, int64_t) const {
+        constexpr int cx = cdir(I, 0), cy = cdir(I, 1), cz = cdir(I, 2);
+        int xs = l.x - cx, ys = l.y - cy, zs = l.z - cz;
+        if (cx > 0 && xs < 0) xs += nx;
+        if (cx < 0 && xs >= nx) xs -= nx;
+        if (cy > 0 && ys < 0) ys += ny;
+        if (cy < 0 && ys >= ny) ys -= ny;
+        if (cz > 0 && zs < 0) zs += nz;
+        if (cz < 0 && zs >= nz) zs -= nz;
+        const int64_t wi = ((int64_t)zs * ny + ys) * W + (xs >> 6);
+        const uint64_t bits = rowbits[wi];
+        const int b = xs & 63;
+        const int32_t base = wordbase[wi];
+        const int64_t idx = base + __popcll(bits & ((1ull << b) - 1ull));
+        return ((bits >> b) & 1ull) ? idx : (int64_t)-1;
+    }
+};
+
+// ------------------------------------------------------------------ moments
+// Moments of 19 values in the paper's order (rho, e, eps, jx, qx, jy, qy, jz,
+// qz, 3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz): the rows of
+// d'Humieres et al. (2002) evaluated on pair sums P_k = f_{2k-1} + f_{2k}
+// (even rows) and differences D_k = f_{2k-1} - f_{2k} (odd rows).
+struct Mom {
+    float rho, e, eps, jx, qx, jy, qy, jz, qz, pxx, pixx, pww, piww, pxy, pyz, pxz, mx, my, mz;
+};
+
+__device__ __forceinline__ Mom moments(const float f[19]) {
+    const float P1 = f[1] + f[2], P2 = f[3] + f[4], P3 = f[5] + f[6];
+    const float P4 = f[7] + f[8], P5 = f[9] + f[10], P6 = f[11] + f[12], P7 = f[13] + f[14];
+    const float P8 = f[15] + f[16], P9 = f[17] + f[18];
+    const float D1 = f[1] - f[2], D2 = f[3] - f[4], D3 = f[5] - f[6];
+    const float D4 = f[7] - f[8], D5 = f[9] - f[10], D6 = f[11] - f[12], D7 = f[13] - f[14];
+    const float D8 = f[15] - f[16], D9 = f[17] - f[18];
+    const float Pa = P1 + P2 + P3;               // |c|^2 = 1
+    const float Pxy = P4 + P5, Pxz = P6 + P7, Pyz = P8 + P9;
+    const float Pd = Pxy + Pxz + Pyz;            // |c|^2 = 2
+    Mom m;
+    m.rho = f[0] + Pa + Pd;
+    m.e = -30.f * f[0] - 11.f * Pa + 8.f * Pd;
+    m.eps = 12.f * f[0] - 4.f * Pa + Pd;
+    m.pxx = 2.f * P1 - P2 - P3 + Pxy + Pxz - 2.f * Pyz;
+    m.pixx = -4.f * P1 + 2.f * (P2 + P3) + Pxy + Pxz - 2.f * Pyz;
+    m.pww = P2 - P3 + Pxy - Pxz;
+    m.piww = -2.f * (P2 - P3) + Pxy - Pxz;
+    m.pxy = P4 - P5;
+    m.pxz = P6 - P7;
+    m.pyz = P8 - P9;
+    const float sx = D4 + D5 + D6 + D7, sy = D4 - D5 + D8 + D9, sz = D6 - D7 + D8 - D9;
+    m.jx = D1 + sx;
+    m.qx = -4.f * D1 + sx;
+    m.jy = D2 + sy;
+    m.qy = -4.f * D2 + sy;
+    m.jz = D3 + sz;
+    m.qz = -4.f * D3 + sz;
+    m.mx = D4 + D5 - D6 - D7;
+    m.my = -D4 + D5 + D8 + D9;
+    m.mz = D6 - D7 - D8 + D9;
+    return m;
+}
+
+// f_i += sum_k M_ki h_k  (h in moment order; M^T applied on pair halves).
+__device__ __forceinline__ void add_back(float f[19], const Mom& h) {
+    f[0] += h.rho - 30.f * h.e + 12.f * h.eps;
+    const float base1 = h.rho - 11.f * h.e - 4.f * h.eps;
+    const float Ex = base1 + 2.f * h.pxx - 4.f * h.pixx;
+    const float Eyz = base1 - h.pxx + 2.f * h.pixx;
+    const float Ey = Eyz + h.pww - 2.f * h.piww;
+    const float Ez = Eyz - h.pww + 2.f * h.piww;
+    const float base2 = h.rho + 8.f * h.e + h.eps;
+    const float Exy = base2 + h.pxx + h.pixx + h.pww + h.piww;
+    const float Exz = base2 + h.pxx + h.pixx - h.pww - h.piww;
+    const float Eyz2 = base2 - 2.f * h.pxx - 2.f * h.pixx;
+    const float Ox = h.jx - 4.f * h.qx, Oy = h.jy - 4.f * h.qy, Oz = h.jz - 4.f * h.qz;
+    const float ax = h.jx + h.qx, ay = h.jy + h.qy, az = h.jz + h.qz;
+    const float O4 = ax + ay + h.mx - h.my;
+    const float O5 = ax - ay + h.mx + h.my;
+    const float O6 = ax + az - h.mx + h.mz;
+    const float O7 = ax - az - h.mx - h.mz;
+    const float O8 = ay + az + h.my - h.mz;
+    const float O9 = ay - az + h.my + h.mz;
+    f[1] += Ex + Ox;            f[2] += Ex - Ox;
+    f[3] += Ey + Oy;            f[4] += Ey - Oy;
+    f[5] += Ez + Oz;            f[6] += Ez - Oz;
+    f[7] += Exy + h.pxy + O4;   f[8] += Exy + h.pxy - O4;
+    f[9] += Exy - h.pxy + O5;   f[10] += Exy - h.pxy - O5;
+    f[11] += Exz + h.pxz + O6;  f[12] += Exz + h.pxz - O6;
+    f[13] += Exz - h.pxz + O7;  f[14] += Exz - h.pxz - O7;
+    f[15] += Eyz2 + h.pyz + O8; f[16] += Eyz2 + h.pyz - O8;
+    f[17] += Eyz2 - h.pyz + O9; f[18] += Eyz2 - h.pyz - O9;
+}
+
+// Squared row norms of M: 19, 2394, 252, 10, 40, 36, 72, 12, 24, 4, 8.
+constexpr float kInvE = 1.f / 2394.f, kInvEps = 1.f / 252.f, kInvJ = 1.f / 10.f,
+                kInvQ = 1.f / 40.f, kInvPxx = 1.f / 36.f, kInvPixx = 1.f / 72.f,
+                kInvPww = 1.f / 12.f, kInvPiww = 1.f / 24.f, kInvP = 1.f / 4.f, kInvM = 1.f / 8.f;
+
+// Post-collision moment increments (m* - m) of the MRT collision with Guo
+// forcing: dm_k = -s_k (m_k - m_eq_k) + (1 - s_k/2) mF_k, where m_eq uses the
+// shifted momentum j = sum f c + F/2 (rho0 = 1, incompressible form with the
+// misprints of Eq. MRT Equi read as corrected) and mF = M F_i in closed form
+// (mF = d m_eq / d j . F).  Returned scaled by 1/|row|^2, ready for add_back.
+__device__ __forceinline__ Mom collide_increment(const Mom& m, float jx, float jy, float jz,
+                                                 float Fx, float Fy, float Fz, const RatesF& r) {
+    const float xx = jx * jx, yy = jy * jy, zz = jz * jz, jj = xx + yy + zz;
+    const float uF = jx * Fx + jy * Fy + jz * Fz;
+    const float pxx_eq = 2.f * xx - yy - zz, pww_eq = yy - zz;
+    const float X = 2.f * jx * Fx - jy * Fy - jz * Fz, Wf = jy * Fy - jz * Fz;
+    const float ge = 1.f - 0.5f * r.s_e, geps = 1.f - 0.5f * r.s_eps, gq = 1.f - 0.5f * r.s_q,
+                gnu = 1.f - 0.5f * r.s_nu, gpi = 1.f - 0.5f * r.s_pi;
+    Mom h;
+    h.rho = 0.f;
+    h.e = (-r.s_e * (m.e - (-11.f * m.rho + 19.f * jj)) + ge * 38.f * uF) * kInvE;
+    h.eps = (-r.s_eps * (m.eps - (3.f * m.rho - 5.5f * jj)) - geps * 11.f * uF) * kInvEps;
+    h.jx = Fx * kInvJ;
+    h.jy = Fy * kInvJ;
+    h.jz = Fz * kInvJ;
+    const float tq = -2.f / 3.f;
+    h.qx = (-r.s_q * (m.qx - tq * jx) + gq * tq * Fx) * kInvQ;
+    h.qy = (-r.s_q * (m.qy - tq * jy) + gq * tq * Fy) * kInvQ;
+    h.qz = (-r.s_q * (m.qz - tq * jz) + gq * tq * Fz) * kInvQ;
+    h.pxx = (-r.s_nu * (m.pxx - pxx_eq) + gnu * 2.f * X) * kInvPxx;
+    h.pixx = (-r.s_pi * (m.pixx + 0.5f * pxx_eq) - gpi * X) * kInvPixx;
+    h.pww = (-r.s_nu * (m.pww - pww_eq) + gnu * 2.f * Wf) * kInvPww;
+    h.piww = (-r.s_pi * (m.piww + 0.5f * pww_eq) - gpi * Wf) * kInvPiww;
+    h.pxy = (-r.s_nu * (m.pxy - jx * jy) + gnu * (jx * Fy + jy * Fx)) * kInvP;
+    h.pyz = (-r.s_nu * (m.pyz - jy * jz) + gnu * (jy * Fz + jz * Fy)) * kInvP;
+    h.pxz = (-r.s_nu * (m.pxz - jx * jz) + gnu * (jx * Fz + jz * Fx)) * kInvP;
+    h.mx = -r.s_m * m.mx * kInvM;
+    h.my = -r.s_m * m.my * kInvM;
+    h.mz = -r.s_m * m.mz * kInvM;
+    return h;
+}
+
+// ------------------------------------------------------------------ reductions
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
+    __shared__ double red[kThreads / 64][K];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// Node range of a block: fixed contiguous chunks of 256 nodes, with logical
+// block ids remapped so that each XCD owns a contiguous part of the list
+// (neighbouring rows then share that XCD's L2).
+__device__ __forceinline__ void block_range(int64_t nf, int& lb, int64_t& c0, int64_t& c1) {
+    const int G = gridDim.x, b = blockIdx.x;
+    lb = (G % kXcds == 0) ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
+    const int64_t chunks = (nf + kThreads - 1) / kThreads;
+    c0 = chunks * lb / G;
+    c1 = chunks * (lb + 1) / G;
+}
+
+// Fixed-order FP64 sum of per-block partials [grid][K] into out[0..K-1], by
+// one whole block: strided per-thread sums, then the block_sum tree.
+template <int K>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ partials, int grid,
+                                                double* __restrict__ out) {
+    double s[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k] = 0.0;
+    for (int b = threadIdx.x; b < grid; b += kThreads)
+#pragma unroll
+        for (int k = 0; k < K; ++k) s[k] += partials[(int64_t)b * K + k];
+    block_sum<K>(s, out);
+}
+
+template <int K>
+__global__ void __launch_bounds__(kThreads)
+k_finalize(const double* __restrict__ partials, int grid, double* __restrict__ out) {
+    reduce_partials<K>(partials, grid, out);
+}
+
+// ------------------------------------------------------------------ step
+template <class C, class Ix, bool FIELD>
+__global__ void __launch_bounds__(kThreads)
+k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
+       int64_t stride, int64_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
+       const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
+       const double* __restrict__ prev_partials, double* __restrict__ prev_out) {
+    // The previous step's block partials are reduced here, by the first block,
+    // so a time step is a single launch; kernel order makes them visible.
+    if (prev_out != nullptr && blockIdx.x == 0) {
+        reduce_partials<4>(prev_partials, gridDim.x, prev_out);
+        __syncthreads();
+    }
+    int lb;
+    int64_t c0, c1;
+    block_range(nf, lb, c0, c1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = c0; c < c1; ++c) {
+        const int64_t n = c * kThreads + threadIdx.x;
+        if (n >= nf) continue;
+        const auto loc = ix.locate(n);
+        float f[19];
+        f[0] = C::ld(src, n, inv);
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            const int64_t s = ix.template src<i>(loc, n);
+            const int64_t a = s >= 0 ? (int64_t)i * stride + s : (int64_t)opp(i) * stride + n;
+            f[i] = C::ld(src, a, inv);
+        });
+        float Fx = Fx0, Fy = Fy0, Fz = Fz0;
+        if (FIELD) {
+            Fx = field[n];
+            Fy = field[nf + n];
+            Fz = field[2 * nf + n];
+        }
+        const Mom m = moments(f);
+        const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
+        acc[0] += (double)jx;
+        acc[1] += (double)jy;
+        acc[2] += (double)jz;
+        acc[3] += (double)m.rho;
+        add_back(f, collide_increment(m, jx, jy, jz, Fx, Fy, Fz, r));
+        unroll<19>([&](auto k) {
+            constexpr int i = decltype(k)::value;
+            C::st(dst, (int64_t)i * stride + n, f[i], scale);
+        });
+    }
+    block_sum<4>(acc, partials + (int64_t)lb * 4);
+}
+
+__global__ void k_zero(uint32_t* p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+template <class C>
+__global__ void k_rescale(typename C::T* p, int64_t count, float factor) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x)
+        C::st(p, i, C::ld(p, i, 1.f), factor);
+}
+
+// ------------------------------------------------------------------ adjoint
+// Quadratic part of the j-derivative of the equilibrium moments, contracted
+// with moment-space weights w: G_a(v, w) = sum_l w_l d m_eq_l / d j_a at j = v.
+struct Vec3 {
+    float x, y, z;
+};
+__device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w) {
+    Vec3 g;
+    const float ee = 38.f * w.e - 11.f * w.eps;
+    g.x = ee * vx + 4.f * vx * w.pxx - 2.f * vx * w.pixx + vy * w.pxy + vz * w.pxz;
+    g.y = ee * vy - 2.f * vy * w.pxx + vy * w.pixx + 2.f * vy * w.pww - vy * w.piww +
+          vx * w.pxy + vz * w.pyz;
+    g.z = ee * vz - 2.f * vz * w.pxx + vz * w.pixx - 2.f * vz * w.pww + vz * w.piww +
+          vy * w.pyz + vx * w.pxz;
+    return g;
+}
+
+// Reverse step n at every node:
+//   b = P^T a^{n+1}            (transpose of the pull stream: gather from x + c_i)
+//   f = P fh^{n-1}             (the forward's gathered populations of step n)
+//   a^n = b + M^T nu,  nu = (d dm / d m)^T D^-1 M b
+// plus the rate-class and body-force sensitivities b^T dC/ds, b^T dC/dF.
+template <class Ix, bool FIELD>
+__global__ void __launch_bounds__(kThreads)
+k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* __restrict__ st,
+          Ix ix, int64_t stride, int64_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
+          const float* __restrict__ field, double* __restrict__ dkdF, double* __restrict__ partials) {
+    int lb;
+    int64_t c0, c1;
+    block_range(nf, lb, c0, c1);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t c = c0; c < c1; ++c) {
+        const int64_t n = c * kThreads + threadIdx.x;
+        if (n >= nf) continue;
+        const auto loc = ix.locate(n);
+        float f[19], b[19];
+        f[0] = st[n];
+        b[0] = ain[n];
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            const int64_t s = ix.template src<i>(loc, n);
+            f[i] = st[s >= 0 ? (int64_t)i * stride + s : (int64_t)opp(i) * stride + n];
+            // adjoint of the pull: a value pulled by the node at x + c_i from x
+            const int64_t t = ix.template src<opp(i)>(loc, n);
+            b[i] = ain[t >= 0 ? (int64_t)i * stride + t : (int64_t)opp(i) * stride + n];
+        });
+        float Fx = Fx0, Fy = Fy0, Fz = Fz0;
+        if (FIELD) {
+            Fx = field[n];
+            Fy = field[nf + n];
+            Fz = field[2 * nf + n];
+        }
+        const Mom m = moments(f);
+        const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
+        const float xx = jx * jx, yy = jy * jy, zz = jz * jz, jj = xx + yy + zz;
+        const float uF = jx * Fx + jy * Fy + jz * Fz;
+        const float pxx_eq = 2.f * xx - yy - zz, pww_eq = yy - zz;
+        const float X = 2.f * jx * Fx - jy * Fy - jz * Fz, Wf = jy * Fy - jz * Fz;
+        Mom mu = moments(b);
+        mu.rho *= 1.f / 19.f;
+        mu.e *= kInvE;
+        mu.eps *= kInvEps;
+        mu.jx *= kInvJ;
+        mu.jy *= kInvJ;
+        mu.jz *= kInvJ;
+        mu.qx *= kInvQ;
+        mu.qy *= kInvQ;
+        mu.qz *= kInvQ;
+        mu.pxx *= kInvPxx;
+        mu.pixx *= kInvPixx;
+        mu.pww *= kInvPww;
+        mu.piww *= kInvPiww;
+        mu.pxy *= kInvP;
+        mu.pyz *= kInvP;
+        mu.pxz *= kInvP;
+        mu.mx *= kInvM;
+        mu.my *= kInvM;
+        mu.mz *= kInvM;
+        // rate-class sensitivities: mu_l * (-(m_l - m_eq_l) - mF_l / 2)
+        acc[0] += (double)(mu.e * (-(m.e - (-11.f * m.rho + 19.f * jj)) - 19.f * uF));
+        acc[1] += (double)(mu.eps * (-(m.eps - (3.f * m.rho - 5.5f * jj)) + 5.5f * uF));
+        const float tq = -2.f / 3.f;
+        acc[2] += (double)(mu.qx * (-(m.qx - tq * jx) + Fx / 3.f) +
+                           mu.qy * (-(m.qy - tq * jy) + Fy / 3.f) +
+                           mu.qz * (-(m.qz - tq * jz) + Fz / 3.f));
+        acc[3] += (double)(mu.pxx * (-(m.pxx - pxx_eq) - X) + mu.pww * (-(m.pww - pww_eq) - Wf) +
+                           mu.pxy * (-(m.pxy - jx * jy) - 0.5f * (jx * Fy + jy * Fx)) +
+                           mu.pyz * (-(m.pyz - jy * jz) - 0.5f * (jy * Fz + jz * Fy)) +
+                           mu.pxz * (-(m.pxz - jx * jz) - 0.5f * (jx * Fz + jz * Fx)));
+        acc[4] += (double)(mu.pixx * (-(m.pixx + 0.5f * pxx_eq) + 0.5f * X) +
+                           mu.piww * (-(m.piww + 0.5f * pww_eq) + 0.5f * Wf));
+        acc[5] += (double)(-(mu.mx * m.mx + mu.my * m.my + mu.mz * m.mz));
+        // c_l = s_l mu_l (equilibrium path), d_l = (1 - s_l/2) mu_l (source path)
+        Mom cw, dw;
+        cw.e = r.s_e * mu.e;       dw.e = (1.f - 0.5f * r.s_e) * mu.e;
+        cw.eps = r.s_eps * mu.eps; dw.eps = (1.f - 0.5f * r.s_eps) * mu.eps;
+        cw.pxx = r.s_nu * mu.pxx;  dw.pxx = (1.f - 0.5f * r.s_nu) * mu.pxx;
+        cw.pixx = r.s_pi * mu.pixx; dw.pixx = (1.f - 0.5f * r.s_pi) * mu.pixx;
+        cw.pww = r.s_nu * mu.pww;  dw.pww = (1.f - 0.5f * r.s_nu) * mu.pww;
+        cw.piww = r.s_pi * mu.piww; dw.piww = (1.f - 0.5f * r.s_pi) * mu.piww;
+        cw.pxy = r.s_nu * mu.pxy;  dw.pxy = (1.f - 0.5f * r.s_nu) * mu.pxy;
+        cw.pyz = r.s_nu * mu.pyz;  dw.pyz = (1.f - 0.5f * r.s_nu) * mu.pyz;
+        cw.pxz = r.s_nu * mu.pxz;  dw.pxz = (1.f - 0.5f * r.s_nu) * mu.pxz;
+        const float cqx = r.s_q * mu.qx, cqy = r.s_q * mu.qy, cqz = r.s_q * mu.qz;
+        const float gq = 1.f - 0.5f * r.s_q;
+        const Vec3 gjc = gquad(jx, jy, jz, cw);
+        const Vec3 gFd = gquad(Fx, Fy, Fz, dw);
+        const Vec3 gjd = gquad(jx, jy, jz, dw);
+        Mom nu;
+        nu.rho = -11.f * cw.e + 3.f * cw.eps;
+        nu.jx = gjc.x + gFd.x + tq * cqx;
+        nu.jy = gjc.y + gFd.y + tq * cqy;
+        nu.jz = gjc.z + gFd.z + tq * cqz;
+        nu.e = -r.s_e * mu.e;
+        nu.eps = -r.s_eps * mu.eps;
+        nu.qx = -r.s_q * mu.qx;
+        nu.qy = -r.s_q * mu.qy;
+        nu.qz = -r.s_q * mu.qz;
+        nu.pxx = -r.s_nu * mu.pxx;
+        nu.pixx = -r.s_pi * mu.pixx;
+        nu.pww = -r.s_nu * mu.pww;
+        nu.piww = -r.s_pi * mu.piww;
+        nu.pxy = -r.s_nu * mu.pxy;
+        nu.pyz = -r.s_nu * mu.pyz;
+        nu.pxz = -r.s_nu * mu.pxz;
+        nu.mx = -r.s_m * mu.mx;
+        nu.my = -r.s_m * mu.my;
+        nu.mz = -r.s_m * mu.mz;
+        // body force: F enters through the shift j = m_j + F/2, through
+        // mF = (d m_eq / d j) F, and directly as the momentum source.
+        const float gFx = 0.5f * nu.jx + gjd.x + tq * gq * mu.qx + mu.jx;
+        const float gFy = 0.5f * nu.jy + gjd.y + tq * gq * mu.qy + mu.jy;
+        const float gFz = 0.5f * nu.jz + gjd.z + tq * gq * mu.qz + mu.jz;
+        dkdF[n] += (double)gFx;
+        dkdF[nf + n] += (double)gFy;
+        dkdF[2 * nf + n] += (double)gFz;
+        add_back(b, nu);
+        unroll<19>([&](auto k) {
+            constexpr int i = decltype(k)::value;
+            aout[(int64_t)i * stride + n] = b[i];
+        });
+    }
+    double part[6];
+    block_sum<6>(acc, part);
+    if ((int)threadIdx.x < 6) partials[(int64_t)lb * 6 + threadIdx.x] += part[threadIdx.x];
+}
+
+__global__ void k_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nf;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        for (int i = 0; i < 19; ++i) adj[(int64_t)i * stride + n] = kappa * (float)cdir(i, axis);
+    }
+}
+
+__global__ void k_add_uniform(double* d, int64_t nf, double vx, double vy, double vz) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nf;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        d[n] += vx;
+        d[nf + n] += vy;
+        d[2 * nf + n] += vz;
+    }
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + kThreads - 1) / kThreads;
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+TableIdx table_view(const IndexView& v) { return TableIdx{v.table, v.stride}; }
+BitmapIdx bitmap_view(const IndexView& v) {
+    return BitmapIdx{v.coords, v.rowbits, v.wordbase, v.nx, v.ny, v.nz, v.W, v.bx, v.by};
+}
+
+template <class C, class Ix>
+hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
+    using T = typename C::T;
+    const T* src = static_cast<const T*>(a.src);
+    T* dst = static_cast<T*>(a.dst);
+    if (a.field)
+        hipLaunchKernelGGL((k_step<C, Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
+                           a.idx.stride, a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
+                           a.inv_scale, a.partials, a.prev_partials, a.prev_out);
+    else
+        hipLaunchKernelGGL((k_step<C, Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
+                           ix, a.idx.stride, a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
+                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.prev_out);
+    return hipGetLastError();
+}
+
+template <class C>
+hipError_t step_codec(const StepLaunch& a, hipStream_t s) {
+    if (a.idx.kind == kTable) return step_with<C>(a, table_view(a.idx), s);
+    return step_with<C>(a, bitmap_view(a.idx), s);
+}
+
+template <class Ix>
+hipError_t adjoint_with(const AdjLaunch& a, Ix ix, hipStream_t s) {
+    if (a.field)
+        hipLaunchKernelGGL((k_adjoint<Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
+                           a.adj_out, a.state, ix, a.idx.stride, a.nf, a.rates, a.F[0], a.F[1],
+                           a.F[2], a.field, a.dk_dF, a.partials);
+    else
+        hipLaunchKernelGGL((k_adjoint<Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
+                           a.adj_out, a.state, ix, a.idx.stride, a.nf, a.rates, a.F[0], a.F[1],
+                           a.F[2], nullptr, a.dk_dF, a.partials);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_step(const StepLaunch& a, hipStream_t s) {
+    switch (a.storage) {
+        case kF32: return step_codec<CodecF32>(a, s);
+        case kF16: return step_codec<CodecF16>(a, s);
+        case kBF16: return step_codec<CodecBF16>(a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kThreads), 0, s, partials, grid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize6(const double* partials, int grid, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize<6>, dim3(1), dim3(kThreads), 0, s, partials, grid, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s) {
+    const int64_t words = (bytes + 3) / 4;
+    hipLaunchKernelGGL(k_zero, dim3(grid_for(words)), dim3(kThreads), 0, s,
+                       static_cast<uint32_t*>(p), words);
+    return hipGetLastError();
+}
+
+hipError_t launch_rescale(int storage, void* p, int64_t count, float factor, hipStream_t s) {
+    const dim3 g(grid_for(count)), b(kThreads);
+    switch (storage) {
+        case kF32:
+            hipLaunchKernelGGL(k_rescale<CodecF32>, g, b, 0, s, static_cast<float*>(p), count, factor);
+            break;
+        case kF16:
+            hipLaunchKernelGGL(k_rescale<CodecF16>, g, b, 0, s, static_cast<_Float16*>(p), count,
+                               factor);
+            break;
+        case kBF16:
+            hipLaunchKernelGGL(k_rescale<CodecBF16>, g, b, 0, s, static_cast<uint16_t*>(p), count,
+                               factor);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(const AdjLaunch& a, hipStream_t s) {
+    if (a.idx.kind == kTable) return adjoint_with(a, table_view(a.idx), s);
+    return adjoint_with(a, bitmap_view(a.idx), s);
+}
+
+hipError_t launch_adjoint_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(nf)), dim3(kThreads), 0, s, adj, stride, nf, axis,
+                       kappa);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_uniform(double* d, int64_t nf, double vx, double vy, double vz,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_add_uniform, dim3(grid_for(nf)), dim3(kThreads), 0, s, d, nf, vx, vy, vz);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

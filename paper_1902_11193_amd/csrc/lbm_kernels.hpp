@@ -1,0 +1,85 @@
+// Launch interface of the gfx950 kernels (host-callable, no HIP types beyond
+// the stream).  Implemented in lbm_kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+enum IndexKind : int { kTable = 0, kBitmap = 1 };
+
+struct RatesF {
+    float s_e, s_eps, s_q, s_nu, s_pi, s_m;
+};
+
+// Device view of the neighbour index.
+struct IndexView {
+    int kind;
+    int64_t stride;             // padded node count (row stride of [19][np] arrays)
+    const int32_t* table;       // kTable: [18][stride]
+    const uint32_t* coords;     // kBitmap: [nf]
+    const uint64_t* rowbits;    // kBitmap: [ny*nz*W]
+    const int32_t* wordbase;    // kBitmap: [ny*nz*W]
+    int nx, ny, nz, W, bx, by;  // kBitmap geometry
+};
+
+struct StepLaunch {
+    int storage;
+    const void* src;      // [19][stride] deviations (storage type)
+    void* dst;            // [19][stride]
+    IndexView idx;
+    int64_t nf;
+    RatesF rates;
+    float F[3];           // uniform force density
+    const float* field;   // optional [3][nf] accelerations (rho0 = 1), or nullptr
+    float scale, inv_scale;
+    int grid;             // number of blocks (fixed per context)
+    double* partials;     // [grid][4] written by this step
+    const double* prev_partials;  // [grid][4] of the previous step, reduced by block 0 ...
+    double* prev_out;             // ... into prev_out[0..3]; nullptr: nothing pending
+};
+
+// One fused step: gather with halfway bounce-back, MRT + Guo collision, store,
+// and per-block FP64 partial sums of (ux, uy, uz, drho).
+hipError_t launch_step(const StepLaunch& a, hipStream_t s);
+
+// Sum the per-block partials in fixed order into out[0..3].
+hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s);
+
+// Fill count elements of `bytes_per_elem` size with zero bits.
+hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
+
+// Multiply every stored deviation by `factor` (storage-exponent change).
+hipError_t launch_rescale(int storage, void* p, int64_t count, float factor, hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint
+struct AdjLaunch {
+    const float* adj_in;   // a^{n+1}: [19][stride] adjoint of the gathered populations of step n+1
+    float* adj_out;        // a^n
+    const float* state;    // fh^{n-1}: [19][stride] FP32 deviations
+    IndexView idx;
+    int64_t nf;
+    RatesF rates;
+    float F[3];
+    const float* field;
+    double* dk_dF;         // [3][nf] accumulated in place (FP64)
+    int grid;
+    double* partials;      // [grid][6] accumulated in place: rate-class sensitivities
+};
+hipError_t launch_adjoint_step(const AdjLaunch& a, hipStream_t s);
+
+// a^N seed: adj[i][n] = kappa * c_i[axis] for fluid nodes.
+hipError_t launch_adjoint_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa,
+                               hipStream_t s);
+
+// out[k] = sum over blocks of partials[b][k], k < 6, fixed order.
+hipError_t launch_finalize6(const double* partials, int grid, double* out, hipStream_t s);
+
+// dk_dF[a][n] += v[a] for every node (direct terms of the readout).
+hipError_t launch_add_uniform(double* dk_dF, int64_t nf, double vx, double vy, double vz,
+                              hipStream_t s);
+
+}  // namespace lbm

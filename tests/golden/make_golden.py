@@ -1,0 +1,56 @@
+"""Writes tests/golden/sc_sphere_32.json with the FP64 oracle only.
+
+The 32^3 periodic box with one solid sphere of radius 8 voxels (simple-cubic
+array), g = (1e-6, 0, 0), tau = 1, Set E with Lambda = 3/16: the per-step
+mean velocity is recorded and the run stops when the per-step relative change
+of <u_x> falls below 1e-9 or after 5000 steps.
+Run: python tests/golden/make_golden.py
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from lbm_inputs import workload  # noqa: E402
+
+
+def main():
+    m = workload("sc_sphere_32")
+    p = O.Problem(m, 1.0, 3 / 16, "E", (1e-6, 0.0, 0.0))
+    fh = p.initial()
+    hist = []
+    prev = None
+    t0 = time.time()
+    steps = 0
+    for n in range(1, 5001):
+        fh, u = p.step(fh)
+        ux = float(p.mean_velocity(u)[0])
+        hist.append(ux)
+        steps = n
+        if n % 500 == 0:
+            print(n, ux, time.time() - t0, flush=True)
+        if prev is not None and abs(ux - prev) < 1e-9 * abs(ux):
+            break
+        prev = ux
+    nu = (1.0 - 0.5) / 3
+    out = dict(
+        about="FP64 oracle, sc_sphere_32 workload (32^3, one sphere R=8 centred at 15.5), tau=1, "
+              "Set E Lambda=3/16, g=(1e-6,0,0); written by tests/golden/make_golden.py",
+        steps=steps,
+        converged=steps < 5000,
+        n_solid=int(m.sum()),
+        k_final=nu * hist[-1] / 1e-6,
+        umean_x={str(n): hist[n - 1] for n in (1, 2, 10, 100, 500, 1000, 2000, steps) if n <= steps},
+    )
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sc_sphere_32.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
+if __name__ == "__main__":
+    main()

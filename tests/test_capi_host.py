@@ -1,0 +1,150 @@
+"""Host-side checks of the C-ABI library: loads, exports what include/lbm.h
+declares, host logic (rates, neighbour table) and argument validation.  No
+call here reaches the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1902_11193_amd as P
+from lbm_inputs import random_mask, sphere, slit
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "lbm.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(P.SIGNATURES) == names
+
+
+def test_velocity_order_matches_header_and_pairs():
+    c = P.lbm_velocities()
+    txt = open(HEADER).read()
+    doc = [tuple(int(v) for v in m) for m in re.findall(r"\d+:\(\s*(-?\d),\s*(-?\d),\s*(-?\d)\)", txt)]
+    assert [tuple(r) for r in c] == doc[:19]
+    for i in range(1, 19, 2):
+        assert np.array_equal(c[i], -c[i + 1])
+    oc = {tuple(v.tolist()) for v in O.velocities()}
+    assert {tuple(r) for r in c} == oc
+
+
+@pytest.mark.parametrize("rset", list(P.SETS))
+@pytest.mark.parametrize("tau", [0.6, 1.0, 1.37])
+def test_rates_match_oracle_and_derivatives(rset, tau):
+    Lam = 0.21
+    s, dt, dl = P.lbm_rates(rset, tau, Lam)
+    want = O.rates(rset, tau, Lam if rset == "E" else None).numpy()
+    assert np.allclose(s, want, rtol=0, atol=1e-15)
+    h = 1e-6
+    sp, _, _ = P.lbm_rates(rset, tau + h, Lam)
+    sm, _, _ = P.lbm_rates(rset, tau - h, Lam)
+    assert np.allclose(dt, (sp - sm) / (2 * h), atol=1e-8)
+    if rset == "E":
+        sp, _, _ = P.lbm_rates(rset, tau, Lam + h)
+        sm, _, _ = P.lbm_rates(rset, tau, Lam - h)
+        assert np.allclose(dl, (sp - sm) / (2 * h), atol=1e-8)
+    else:
+        assert not dl.any()
+
+
+def test_rates_reject():
+    for args in (("E", 0.5, 0.2), ("E", 1.0, 0.0), (7, 1.0, 0.2), ("SRT", float("nan"), 0.2)):
+        with pytest.raises(P.LbmError) as e:
+            P.lbm_rates(*args)
+        assert e.value.code == P.LBM_EINVAL
+
+
+def _brute_table(mask):
+    nz, ny, nx = mask.shape
+    c = P.lbm_velocities()
+    fl = np.flatnonzero(mask.reshape(-1) == 0)
+    node = -np.ones(mask.size, np.int64)
+    node[fl] = np.arange(len(fl))
+    z, y, x = np.unravel_index(fl, mask.shape)
+    t = np.empty((18, len(fl)), np.int64)
+    for i in range(1, 19):
+        sx, sy, sz = (x - c[i, 0]) % nx, (y - c[i, 1]) % ny, (z - c[i, 2]) % nz
+        t[i - 1] = node[np.ravel_multi_index((sz, sy, sx), mask.shape)]
+    return t
+
+
+@pytest.mark.parametrize("shape,sf,seed", [((5, 6, 7), 0.3, 0), ((8, 8, 8), 0.5, 1), ((1, 9, 70), 0.2, 2),
+                                           ((3, 2, 130), 0.4, 3)])
+def test_neighbor_table_brute_force_and_permutation(shape, sf, seed):
+    mask = random_mask(shape, sf, seed)
+    if (mask == 0).sum() == 0:
+        mask.flat[0] = 0
+    t = P.lbm_neighbor_table(mask)
+    assert np.array_equal(t, _brute_table(mask))
+    # every post-collision value (j, m) is read exactly once by the pull + bounce-back
+    nf = t.shape[1]
+    reads = np.zeros((19, nf), np.int64)
+    reads[0] += 1
+    for i in range(1, 19):
+        j = i + 1 if i % 2 else i - 1
+        src = t[i - 1]
+        ok = src >= 0
+        np.add.at(reads[i], src[ok], 1)
+        np.add.at(reads[j], np.flatnonzero(~ok), 1)
+    assert (reads == 1).all()
+
+
+def test_workspace_query_counts_and_errors():
+    m = sphere(16, (7.5, 7.5, 7.5), 4.0)
+    nb, nf = P.lbm_workspace_query(m, "f32", "table")
+    assert nf == int((m == 0).sum())
+    nb16, _ = P.lbm_workspace_query(m, "f16", "bitmap")
+    assert nb16 < nb
+    with pytest.raises(P.LbmError) as e:
+        P.lbm_workspace_query(np.ones((4, 4, 4), np.uint8))
+    assert e.value.code == P.LBM_ENOFLUID
+    L = P.lib()
+    g = np.zeros((2, 2, 2), np.uint8)
+    ptr = g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    nbytes, n = ctypes.c_size_t(0), ctypes.c_int64(0)
+    assert L.lbm_workspace_query(ptr, 0, 2, 2, 0, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
+    assert L.lbm_workspace_query(ptr, 2, 2, 2, 3, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
+    assert L.lbm_workspace_query(ptr, 2, 2, 2, 0, 2, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
+    assert L.lbm_workspace_query(None, 2, 2, 2, 0, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
+
+
+def _setup_rc(mask, tau=1.0, Lam=0.1875, rset=5, g=(1e-6, 0, 0), storage=0, index=1, ws=None, nbytes=None):
+    """Call lbm_setup with a fake (never dereferenced) workspace; validation fails first."""
+    L = P.lib()
+    m = np.ascontiguousarray(mask, np.uint8)
+    nz, ny, nx = m.shape
+    ctx = ctypes.c_void_p()
+    gv = (ctypes.c_double * 3)(*g)
+    rc = L.lbm_setup(ctypes.byref(ctx), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), nx, ny, nz, tau, Lam,
+                     rset, gv, storage, index, ws, nbytes if nbytes is not None else 0, None)
+    assert not ctx.value
+    return rc
+
+
+def test_setup_validates_before_any_device_call():
+    m = slit(4, 6, 4, 3)
+    fake = ctypes.c_void_p(4096)  # aligned, never touched: every case fails validation first
+    assert _setup_rc(m, tau=0.5, ws=fake, nbytes=1 << 40) == P.LBM_EINVAL
+    assert _setup_rc(m, tau=float("inf"), ws=fake, nbytes=1 << 40) == P.LBM_EINVAL
+    assert _setup_rc(m, rset=6, ws=fake, nbytes=1 << 40) == P.LBM_EINVAL
+    assert _setup_rc(m, Lam=0.0, ws=fake, nbytes=1 << 40) == P.LBM_EINVAL
+    assert _setup_rc(m, g=(float("nan"), 0, 0), ws=fake, nbytes=1 << 40) == P.LBM_EINVAL
+    assert _setup_rc(m, storage=5, ws=fake, nbytes=1 << 40) == P.LBM_EINVAL
+    assert _setup_rc(np.ones((3, 3, 3)), ws=fake, nbytes=1 << 40) == P.LBM_ENOFLUID
+    assert _setup_rc(m, ws=None, nbytes=1 << 40) == P.LBM_EWORKSPACE
+    assert _setup_rc(m, ws=fake, nbytes=16) == P.LBM_EWORKSPACE
+    assert _setup_rc(m, ws=ctypes.c_void_p(4096 + 8), nbytes=1 << 40) == P.LBM_EWORKSPACE
+    assert b"workspace" in P.lib().lbm_last_error()

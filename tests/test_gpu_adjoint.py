@@ -1,0 +1,89 @@
+"""GPU discrete adjoint against the oracle's FP64 gradient (itself pinned to
+central finite differences), plus properties at full size.
+
+Tolerance: the GPU adjoint runs in FP32 with FP64 accumulation; gradients must
+agree with the FP64 oracle to 1e-4 of their scale (the benchmark spec's bound for
+the adjoint against finite differences)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1902_11193_amd as P
+from gpu_helpers import banner
+from lbm_inputs import random_mask, percolating_x, workload, crop
+
+pytestmark = pytest.mark.gpu
+
+
+def _compare(mask, rset, tau, Lam, g, N, K, index="bitmap"):
+    banner(f"adjoint {mask.shape} {rset} N={N} K={K} {index}")
+    s = P.Solver(mask, tau, Lam, rset, g, "f32", index)
+    r = s.adjoint(N, K)
+    p = O.Problem(mask, tau, Lam, rset, g)
+    o = O.gradients(p, N, segment=max(K, 8))
+    s.close()
+    assert abs(r["k"] / o["k"] - 1) < 1e-5
+    kscale = abs(o["k"])
+    assert abs(r["dk_dtau"] - o["dk_dtau"]) < 1e-4 * max(abs(o["dk_dtau"]), kscale / tau)
+    if rset == "E":
+        assert abs(r["dk_dLambda"] - o["dk_dLambda"]) < 1e-4 * max(abs(o["dk_dLambda"]), kscale)
+    else:
+        assert r["dk_dLambda"] == 0.0
+    dg = r["dk_dg"].cpu().numpy()
+    og = o["dk_dg"].numpy()
+    scale = np.abs(og).max()
+    assert np.abs(dg - og).max() < 1e-4 * scale, np.abs(dg - og).max() / scale
+    return r, o
+
+
+@pytest.mark.parametrize("rset,tau,Lam", [("E", 0.9, 3 / 16), ("SRT", 0.8, None), ("C", 1.2, None)])
+def test_adjoint_matches_oracle_small(rset, tau, Lam):
+    mask = percolating_x(random_mask((6, 7, 9), 0.25, seed=31))
+    _compare(mask, rset, tau, Lam, (1e-5, 2e-6, -1e-6), N=40, K=7)
+
+
+def test_adjoint_table_layout_and_single_segment():
+    mask = percolating_x(random_mask((6, 7, 9), 0.25, seed=32))
+    _compare(mask, "D", 1.0, None, (1e-5, 0, 0), N=25, K=100, index="table")
+    _compare(mask, "E", 1.0, 1 / 12, (1e-5, 0, 0), N=2, K=1, index="table")
+
+
+def test_adjoint_pack_crop_vs_oracle():
+    """32^3 crop of the radius-8 sphere pack (porosity 0.38), 300 steps."""
+    m = crop(workload("pack_128"), 32)
+    _compare(m, "E", 1.0, 3 / 16, (1e-6, 0, 0), N=300, K=40)
+
+
+def test_adjoint_full_size_pack_128_euler_identity():
+    """128^3 pack, 4000 steps, checkpoint every 200: the scheme is linear in g
+    up to O(g) corrections, so sum_x g0 dk/dg(x) = k to ~1e-5; dk/dtau is
+    tiny for Set E (tau-independence)."""
+    m = workload("pack_128")
+    banner("adjoint pack_128 N=4000 K=200")
+    s = P.Solver(m, 1.0, 3 / 16, "E", (1e-6, 0, 0))
+    r = s.adjoint(4000, 200)
+    dg = r["dk_dg"][0].double().sum().item() * 1e-6
+    assert abs(dg / r["k"] - 1) < 1e-4
+    assert abs(r["dk_dtau"]) < 0.05 * r["k"]
+    s.close()
+
+
+def test_autograd_function_matches_solver_adjoint():
+    mask = percolating_x(random_mask((8, 8, 8), 0.3, seed=33))
+    banner("PermeabilityFn")
+    s = P.Solver(mask, 0.9, 0.25, "E", (1e-5, 0, 0))
+    ref = s.adjoint(60, 16)
+    s.close()
+    tau = torch.tensor(0.9, dtype=torch.float64, requires_grad=True)
+    lam = torch.tensor(0.25, dtype=torch.float64, requires_grad=True)
+    nf = int((mask == 0).sum())
+    gfield = torch.zeros((3, nf), dtype=torch.float32, device="cuda")
+    gfield[0] = 1e-5
+    gfield.requires_grad_(True)
+    k = P.permeability(mask, tau, lam, gfield, "E", (1e-5, 0, 0), n_steps=60, checkpoint_every=16)
+    k.backward()
+    assert abs(k.item() / ref["k"] - 1) < 1e-12
+    assert abs(tau.grad.item() - ref["dk_dtau"]) <= 1e-12 * abs(ref["dk_dtau"]) + 1e-300
+    assert abs(lam.grad.item() - ref["dk_dLambda"]) <= 1e-12 * abs(ref["dk_dLambda"])
+    assert torch.allclose(gfield.grad, ref["dk_dg"].float())
