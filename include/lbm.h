@@ -14,8 +14,12 @@
  * Conventions shared by every call
  *   - geometry: uint8 [nz][ny][nx], x fastest; 0 = fluid, any other value =
  *     solid.  The box is periodic in all three axes.
- *   - Only fluid voxels carry populations.  They are numbered 0..n_fluid-1 in
- *     raster order (x fastest) of the voxel image: the "compacted fluid list".
+ *   - Only fluid voxels carry populations.  They are numbered 0..n_fluid-1,
+ *     the "compacted fluid list", in node order: the (y, z) rows of the image
+ *     taken in z-tiles of 16 planes (tile z / 16, then y, then z inside the
+ *     tile), the fluid voxels of each row in increasing x.  Every per-node
+ *     array of this interface (state, force field, gradients, neighbour
+ *     table) uses this order; lbm_node_order gives the voxel of each node.
  *   - Velocity order i = 0..18 (pairs i, i+1 for odd i are opposite):
  *       0:( 0, 0, 0)
  *       1:( 1, 0, 0)  2:(-1, 0, 0)  3:( 0, 1, 0)  4:( 0,-1, 0)
@@ -73,10 +77,11 @@ extern "C" {
 /* Neighbour layout used by the gather.
  * LBM_INDEX_TABLE:  int32 [18][n_pad] table of pull-source nodes (-1 = wall),
  *                   72 bytes per fluid node.
- * LBM_INDEX_BITMAP: one packed uint32 voxel coordinate per node plus a fluid
- *                   bitmap of the image and per-64-voxel prefix counts; the
- *                   source node of a link is found by a population count.
- *                   4 bytes per node + 3 bits per voxel.  Needs
+ * LBM_INDEX_BITMAP: one packed uint32 voxel coordinate per node plus, for
+ *                   every (y, z) row, a 16-byte record per 32 voxels (fluid
+ *                   bits, node number before the word, fluid count of the
+ *                   row); the source node of a link is found by a population
+ *                   count.  4 bytes per node + 4 bits per voxel.  Needs
  *                   ceil(log2 nx) + ceil(log2 ny) + ceil(log2 nz) <= 32. */
 #define LBM_INDEX_TABLE 0
 #define LBM_INDEX_BITMAP 1
@@ -98,6 +103,11 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
  * needs.  Fails with LBM_ENOFLUID / LBM_ERANGE / LBM_EINVAL as lbm_setup. */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
+
+/* Host only (no GPU needed).  Linear voxel id x + nx (y + ny z) of every
+ * node, in node order: voxel[n_fluid] int64, owned by the caller. */
+int lbm_node_order(const uint8_t* geometry, int nx, int ny, int nz, int64_t* voxel,
+                   int64_t n_fluid);
 
 /* Host only (no GPU needed).  The pull-source table of the compacted fluid
  * list: table[(i-1) * n_fluid + n] = node at x_n - c_i (periodic), or -1 when

@@ -31,6 +31,7 @@ SIGNATURES = {
     "lbm_workspace_query": (c_int, [POINTER(c_uint8), c_int, c_int, c_int, c_int, c_int, POINTER(c_size_t),
                                     POINTER(c_int64)]),
     "lbm_neighbor_table": (c_int, [POINTER(c_uint8), c_int, c_int, c_int, POINTER(c_int32), c_int64]),
+    "lbm_node_order": (c_int, [POINTER(c_uint8), c_int, c_int, c_int, POINTER(c_int64), c_int64]),
     "lbm_setup": (c_int, [POINTER(c_void_p), POINTER(c_uint8), c_int, c_int, c_int, c_double, c_double, c_int,
                           POINTER(c_double), c_int, c_int, c_void_p, c_size_t, c_void_p]),
     "lbm_step": (c_int, [c_void_p, c_int]),
@@ -123,6 +124,24 @@ def lbm_neighbor_table(geometry) -> np.ndarray:
     t = np.empty((18, max(nf, 1)), np.int32)
     _check(lib().lbm_neighbor_table(_dptr(g, c_uint8), nx, ny, nz, _dptr(t, c_int32), nf))
     return t[:, :nf]
+
+
+def lbm_node_order(geometry) -> np.ndarray:
+    """Linear voxel id of every node of the compacted fluid list (node order)."""
+    g, nx, ny, nz = _geom(geometry)
+    nf = int(np.count_nonzero(g == 0))
+    v = np.empty(max(nf, 1), np.int64)
+    _check(lib().lbm_node_order(_dptr(g, c_uint8), nx, ny, nz, _dptr(v, c_int64), nf))
+    return v[:nf]
+
+
+def raster_permutation(geometry) -> np.ndarray:
+    """perm with raster_list[perm[k]] = node k: position of every node in the
+    raster-ordered (x fastest) list of fluid voxels."""
+    g = np.ascontiguousarray(geometry, dtype=np.uint8)
+    order = lbm_node_order(g)
+    raster = np.flatnonzero(g.reshape(-1) == 0)
+    return np.searchsorted(raster, order)
 
 
 # ---------------------------------------------------------------- solver
@@ -287,4 +306,4 @@ def permeability(geometry, tau, Lambda, g_field, relaxation_set="E", g_ref=(1e-6
 
 
 __all__ = ["lib", "LbmError", "Solver", "permeability", "lbm_velocities", "lbm_rates", "lbm_workspace_query",
-           "lbm_neighbor_table", "SIGNATURES", "SETS", "STORAGE", "INDEX", "LIB_PATH"]
+           "lbm_neighbor_table", "lbm_node_order", "raster_permutation", "SIGNATURES", "SETS", "STORAGE", "INDEX", "LIB_PATH"]

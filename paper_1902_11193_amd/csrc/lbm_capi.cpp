@@ -44,7 +44,7 @@ size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
-    size_t A, B, table, coords, rowbits, wordbase, partials, ring, total;
+    size_t A, B, table, coords, rec, partials, ring, total;
 };
 
 Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int ny, int nz) {
@@ -59,13 +59,11 @@ Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int n
         L.table = off;
         off += align256((size_t)18 * np * 4);
     } else {
-        const size_t words = (size_t)ny * nz * ((nx + 63) / 64);
+        const size_t recs = (size_t)ny * nz * lbm::records_per_row(nx);
         L.coords = off;
         off += align256((size_t)std::max<int64_t>(nf, 1) * 4);
-        L.rowbits = off;
-        off += align256(words * 8);
-        L.wordbase = off;
-        off += align256(words * 4);
+        L.rec = off;
+        off += align256(recs * sizeof(lbm::RowRec));
     }
     L.partials = off;  // two buffers: steps alternate between them
     off += 2 * align256((size_t)kMaxGrid * 4 * 8);
@@ -249,6 +247,17 @@ int lbm_neighbor_table(const uint8_t* geometry, int nx, int ny, int nz, int32_t*
     return LBM_OK;
 }
 
+int lbm_node_order(const uint8_t* geometry, int nx, int ny, int nz, int64_t* voxel,
+                   int64_t n_fluid) {
+    std::string e = check_common(geometry, nx, ny, nz, LBM_F32, LBM_INDEX_TABLE);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    if (!voxel) return fail(LBM_EINVAL, "voxel is NULL");
+    const int64_t nf = lbm::count_fluid(geometry, nx, ny, nz);
+    if (nf != n_fluid) return fail(LBM_EINVAL, "n_fluid does not match the image");
+    lbm::fluid_voxels(geometry, nx, ny, nz, voxel);
+    return LBM_OK;
+}
+
 int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
               double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
               void* workspace, size_t workspace_bytes, void* hip_stream) {
@@ -315,8 +324,13 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     hipError_t he = hipGetDevice(&dev);
     if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("device query: ") + hipGetErrorString(he)));
+    // One resident wave of blocks: every block starts at once and walks the
+    // chunk list with stride `grid` (rounded to a multiple of the XCD count).
+    int per_cu = 0;
+    if (he == hipSuccess) he = lbm::step_occupancy(storage, index_kind, &per_cu);
+    if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("occupancy query: ") + hipGetErrorString(he)));
     const int64_t chunks = (nf + 255) / 256;
-    int64_t G = std::min<int64_t>(chunks, (int64_t)std::max(cus, 1) * 8);
+    int64_t G = std::min<int64_t>(chunks, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
     if (G >= 64) G -= G % 8;
     c->grid = (int)std::min<int64_t>(G, kMaxGrid);
 
@@ -328,27 +342,24 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     if (index_kind == LBM_INDEX_TABLE) {
         table.assign((size_t)18 * c->np, -1);
         lbm::build_table(geometry, nx, ny, nz, nf, c->np, table.data());
+        lbm::table_to_pull_offsets(table.data(), nf, c->np);
         v.table = reinterpret_cast<const int32_t*>(c->ws + c->L.table);
         he = hipMemcpyAsync(c->ws + c->L.table, table.data(), table.size() * 4,
                             hipMemcpyHostToDevice, c->stream);
     } else {
         lbm::build_bitmap(geometry, nx, ny, nz, nf, &bm);
         v.coords = reinterpret_cast<const uint32_t*>(c->ws + c->L.coords);
-        v.rowbits = reinterpret_cast<const uint64_t*>(c->ws + c->L.rowbits);
-        v.wordbase = reinterpret_cast<const int32_t*>(c->ws + c->L.wordbase);
+        v.rec = c->ws + c->L.rec;
         v.nx = nx;
         v.ny = ny;
         v.nz = nz;
-        v.W = bm.words_per_row;
+        v.R = bm.recs_per_row;
         v.bx = bm.bits.bx;
         v.by = bm.bits.by;
         he = hipMemcpyAsync(c->ws + c->L.coords, bm.coords.data(), bm.coords.size() * 4,
                             hipMemcpyHostToDevice, c->stream);
         if (he == hipSuccess)
-            he = hipMemcpyAsync(c->ws + c->L.rowbits, bm.rowbits.data(), bm.rowbits.size() * 8,
-                                hipMemcpyHostToDevice, c->stream);
-        if (he == hipSuccess)
-            he = hipMemcpyAsync(c->ws + c->L.wordbase, bm.wordbase.data(), bm.wordbase.size() * 4,
+            he = hipMemcpyAsync(c->ws + c->L.rec, bm.rec.data(), bm.rec.size() * sizeof(lbm::RowRec),
                                 hipMemcpyHostToDevice, c->stream);
     }
     if (he == hipSuccess) he = lbm::launch_zero(c->ws + c->L.A, (int64_t)(c->L.B - c->L.A) * 2, c->stream);

@@ -135,6 +135,30 @@ std::vector<int64_t> slab_offsets(const uint8_t* g, int nx, int ny, int nz) {
 }
 }  // namespace
 
+std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
+    const int64_t rows = (int64_t)ny * nz;
+    std::vector<int64_t> cnt(rows, 0), start(rows + 1, 0);
+    parallel_slabs(nz, rows * nx, [&](int z0, int z1) {
+        for (int z = z0; z < z1; ++z)
+            for (int y = 0; y < ny; ++y) {
+                const uint8_t* p = g + ((int64_t)z * ny + y) * nx;
+                int64_t c = 0;
+                for (int x = 0; x < nx; ++x) c += (p[x] == 0);
+                cnt[(int64_t)z * ny + y] = c;
+            }
+    });
+    int64_t n = 0;
+    for (int z0 = 0; z0 < nz; z0 += kNodeTileZ)
+        for (int y = 0; y < ny; ++y)
+            for (int z = z0; z < std::min(nz, z0 + kNodeTileZ); ++z) {
+                const int64_t r = (int64_t)z * ny + y;
+                start[r] = n;
+                n += cnt[r];
+            }
+    start[rows] = n;
+    return start;
+}
+
 int64_t count_fluid(const uint8_t* g, int nx, int ny, int nz) {
     return slab_offsets(g, nx, ny, nz)[nz];
 }
@@ -147,10 +171,14 @@ void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t s
                  int32_t* table) {
     const int64_t plane = (int64_t)nx * ny, vol = plane * nz;
     std::vector<int32_t> node(vol);
-    auto off = slab_offsets(g, nx, ny, nz);
+    auto start = row_starts(g, nx, ny, nz);
     parallel_slabs(nz, vol, [&](int z0, int z1) {
-        int64_t n = off[z0];
-        for (int64_t v = plane * z0; v < plane * z1; ++v) node[v] = g[v] == 0 ? (int32_t)n++ : -1;
+        for (int z = z0; z < z1; ++z)
+            for (int y = 0; y < ny; ++y) {
+                const int64_t r = (int64_t)z * ny + y;
+                int64_t n = start[r];
+                for (int64_t v = r * nx; v < (r + 1) * nx; ++v) node[v] = g[v] == 0 ? (int32_t)n++ : -1;
+            }
     });
     parallel_slabs(nz, vol * 18, [&](int z0, int z1) {
         for (int z = z0; z < z1; ++z)
@@ -174,43 +202,74 @@ void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t s
 }
 
 void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out) {
-    const int W = (nx + 63) / 64;
+    const int R = records_per_row(nx);
     const int64_t rows = (int64_t)ny * nz;
-    out->words_per_row = W;
+    out->recs_per_row = R;
     out->bits = coord_bits(nx, ny, nz);
     out->coords.assign(nf, 0);
-    out->rowbits.assign(rows * W, 0);
-    out->wordbase.assign(rows * W, 0);
-    auto off = slab_offsets(g, nx, ny, nz);
+    out->rec.assign(rows * R, RowRec{0, 0, 0, 0});
+    auto start = row_starts(g, nx, ny, nz);
     const int bx = out->bits.bx, by = out->bits.by;
     parallel_slabs(nz, rows * nx, [&](int z0, int z1) {
-        int64_t n = off[z0];
+        std::vector<uint8_t> pad(nx + 2);
         for (int z = z0; z < z1; ++z)
             for (int y = 0; y < ny; ++y) {
                 const int64_t r = (int64_t)z * ny + y;
                 const uint8_t* p = g + r * nx;
-                for (int w = 0; w < W; ++w) {
-                    out->wordbase[r * W + w] = (int32_t)n;
-                    uint64_t bits = 0;
-                    for (int b = 0; b < 64 && 64 * w + b < nx; ++b) {
-                        const int x = 64 * w + b;
-                        if (p[x] == 0) {
-                            bits |= 1ull << b;
-                            out->coords[n++] = (uint32_t)x | ((uint32_t)y << bx) |
-                                               ((uint32_t)z << (bx + by));
-                        }
+                const int64_t rowstart = start[r];
+                int64_t n = rowstart;
+                for (int x = 0; x < nx; ++x) pad[x + 1] = p[x] == 0;
+                pad[0] = pad[nx];
+                pad[nx + 1] = pad[1];
+                int32_t count = 0;
+                for (int x = 0; x < nx; ++x) count += pad[x + 1];
+                RowRec* rr = out->rec.data() + r * R;
+                int64_t before = 0;  // fluid voxels at real positions [1, 32 w)
+                for (int w = 0; w < R; ++w) {
+                    uint32_t bits = 0;
+                    for (int b = 0; b < kRecBits; ++b) {
+                        const int q = kRecBits * w + b;
+                        if (q < nx + 2 && pad[q]) bits |= 1u << b;
                     }
-                    out->rowbits[r * W + w] = bits;
+                    rr[w].bits = bits;
+                    rr[w].base = (int32_t)(rowstart + before - (w == 0 ? pad[0] : 0));
+                    rr[w].count = count;
+                    rr[w].unused = 0;
+                    for (int b = 0; b < kRecBits; ++b) {
+                        const int q = kRecBits * w + b;
+                        if (q >= 1 && q <= nx) before += pad[q];
+                    }
                 }
+                for (int x = 0; x < nx; ++x)
+                    if (p[x] == 0)
+                        out->coords[n++] =
+                            (uint32_t)x | ((uint32_t)y << bx) | ((uint32_t)z << (bx + by));
             }
     });
 }
 
+void table_to_pull_offsets(int32_t* t, int64_t nf, int64_t stride) {
+    for (int i = 1; i < 19; ++i) {
+        const bool first = (i & 1) != 0;
+        int32_t* row = t + (int64_t)(i - 1) * stride;
+        for (int64_t n = 0; n < nf; ++n) {
+            const int32_t s = row[n];
+            row[n] = s >= 0 ? (int32_t)(s + (first ? 0 : stride)) : (int32_t)(n + (first ? stride : 0));
+        }
+    }
+}
+
 void fluid_voxels(const uint8_t* g, int nx, int ny, int nz, int64_t* out) {
-    const int64_t vol = (int64_t)nx * ny * nz;
-    int64_t n = 0;
-    for (int64_t v = 0; v < vol; ++v)
-        if (g[v] == 0) out[n++] = v;
+    auto start = row_starts(g, nx, ny, nz);
+    parallel_slabs(nz, (int64_t)nx * ny * nz, [&](int z0, int z1) {
+        for (int z = z0; z < z1; ++z)
+            for (int y = 0; y < ny; ++y) {
+                const int64_t r = (int64_t)z * ny + y;
+                int64_t n = start[r];
+                for (int x = 0; x < nx; ++x)
+                    if (g[r * nx + x] == 0) out[n++] = r * nx + x;
+            }
+    });
 }
 
 }  // namespace lbm

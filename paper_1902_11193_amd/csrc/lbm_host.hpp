@@ -34,6 +34,18 @@ struct CoordBits {
 };
 CoordBits coord_bits(int nx, int ny, int nz);
 
+// Node order of the compacted fluid list: the (y, z) rows of the image are
+// taken in z-tiles of kNodeTileZ planes -- tile, then y, then z inside the
+// tile -- and the fluid voxels of each row in increasing x.  Rows that are
+// neighbours in y or z then sit at most kNodeTileZ rows apart in the list
+// (except across tile faces), so the cache lines a step gathers from are
+// reused while still in L2.
+constexpr int kNodeTileZ = 16;
+
+// Node number of the first fluid voxel of every row r = z * ny + y
+// (entry ny * nz holds the fluid count).
+std::vector<int64_t> row_starts(const uint8_t* geom, int nx, int ny, int nz);
+
 // Padded node count: the fluid list rounded up to a multiple of 256.
 inline int64_t padded(int64_t nf) { return (nf + 255) / 256 * 256; }
 
@@ -41,19 +53,38 @@ inline int64_t padded(int64_t nf) { return (nf + 255) / 256 * 256; }
 void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_t stride,
                  int32_t* table);
 
-// Bitmap index: packed coordinate per node, fluid bits per 64-voxel word of
-// every (y, z) row, and the node number of the first fluid voxel at or after
-// each word.
+// Rewrites a pull-source table in place into the device form: the element
+// offset of the gathered population relative to the base of its opposite
+// pair (src + (i odd ? i : i-1) * stride), i.e. s (+ stride for even i) for a
+// fluid source, n (+ stride for odd i) at a wall.
+void table_to_pull_offsets(int32_t* table, int64_t nf, int64_t stride);
+
+// Bitmap index.  Every (y, z) row of the image is a padded bit string of
+// nx + 2 positions: position x + 1 holds voxel x, position 0 repeats voxel
+// nx - 1 and position nx + 1 repeats voxel 0 (the periodic wrap).  It is cut
+// into 32-position words; each word has a 16-byte record with its bits, the
+// node number counting real voxels before the word (minus the left pad bit
+// on word 0) and the row's fluid count.  One extra zero record ends each row
+// so that a 3-position window never reads past it.  Each node also keeps its
+// packed voxel coordinate.
+struct RowRec {
+    uint32_t bits;
+    int32_t base;
+    int32_t count;
+    int32_t unused;
+};
+static_assert(sizeof(RowRec) == 16, "RowRec is one 16-byte load");
+constexpr int kRecBits = 32;
+inline int records_per_row(int nx) { return (nx + 2 + kRecBits - 1) / kRecBits + 1; }
 struct BitmapIndex {
-    int words_per_row = 0;
+    int recs_per_row = 0;
     CoordBits bits{};
-    std::vector<uint32_t> coords;    // [nf]
-    std::vector<uint64_t> rowbits;   // [ny * nz * words_per_row]
-    std::vector<int32_t> wordbase;   // [ny * nz * words_per_row]
+    std::vector<uint32_t> coords;  // [nf]
+    std::vector<RowRec> rec;       // [ny * nz * recs_per_row]
 };
 void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out);
 
-// Linear voxel id of every fluid node (raster order).
+// Linear voxel id x + nx (y + ny z) of every fluid node, in node order.
 void fluid_voxels(const uint8_t* geom, int nx, int ny, int nz, int64_t* out);
 
 }  // namespace lbm

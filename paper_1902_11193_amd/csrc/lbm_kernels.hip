@@ -48,81 +48,220 @@ __device__ __forceinline__ void unroll(F&& f) {
 }
 
 // ------------------------------------------------------------------ codecs
+// Storage of deviations f_i - w_i rho0: cvt decodes a stored value, enc
+// encodes one (FP16 carries a power-of-two scale; BF16 rounds to nearest even).
 struct CodecF32 {
     using T = float;
-    static __device__ __forceinline__ float ld(const T* p, int64_t i, float) { return p[i]; }
-    static __device__ __forceinline__ void st(T* p, int64_t i, float v, float) { p[i] = v; }
+    static __device__ __forceinline__ float cvt(T v, float) { return v; }
+    static __device__ __forceinline__ T enc(float v, float) { return v; }
 };
 struct CodecF16 {
     using T = _Float16;
-    static __device__ __forceinline__ float ld(const T* p, int64_t i, float inv) {
-        return (float)p[i] * inv;
-    }
-    static __device__ __forceinline__ void st(T* p, int64_t i, float v, float s) {
-        p[i] = (_Float16)(v * s);
-    }
+    static __device__ __forceinline__ float cvt(T v, float inv) { return (float)v * inv; }
+    static __device__ __forceinline__ T enc(float v, float s) { return (_Float16)(v * s); }
 };
 struct CodecBF16 {
     using T = uint16_t;
-    static __device__ __forceinline__ float ld(const T* p, int64_t i, float inv) {
-        return __uint_as_float((uint32_t)p[i] << 16) * inv;
+    static __device__ __forceinline__ float cvt(T v, float inv) {
+        return __uint_as_float((uint32_t)v << 16) * inv;
     }
-    static __device__ __forceinline__ void st(T* p, int64_t i, float v, float s) {
+    static __device__ __forceinline__ T enc(float v, float s) {
         const uint32_t u = __float_as_uint(v * s);
-        uint16_t r;
-        if ((u & 0x7fffffffu) > 0x7f800000u)
-            r = (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
-        else
-            r = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);  // round to nearest even
-        p[i] = r;
+        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
+        return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);               // nearest even
     }
 };
+
+// ------------------------------------------------------------------ addressing
+// Loads through a wave-uniform base pointer and a 32-bit byte offset: the
+// compiler emits global loads with a scalar base and one VGPR offset, so no
+// 64-bit address arithmetic runs per lane.
+template <class T>
+__device__ __forceinline__ T ld_off(const T* base, uint32_t byte_off) {
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class T>
+__device__ __forceinline__ void st_off(T* base, uint32_t byte_off, T v) {
+    *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+// Streaming store: the next step reads these values only after the whole
+// population array (gigabytes) has gone through the caches, so they are
+// written without displacing cached lines the gathers still reuse.
+template <class T>
+__device__ __forceinline__ void st_stream(T* base, uint32_t byte_off, T v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
+}
+
+// Element offset of the population gathered in direction i, relative to the
+// base of its opposite pair, src + (i odd ? i : i - 1) * stride: the value
+// pulled from node s, or at a wall the node's own opposite population.
+__device__ __forceinline__ uint32_t pull_offset(int i, int32_t s, uint32_t n, uint32_t stride) {
+    const bool first = (i & 1) != 0;
+    return s >= 0 ? (uint32_t)s + (first ? 0u : stride) : n + (first ? stride : 0u);
+}
+__host__ __device__ constexpr int pair_first(int i) { return (i & 1) ? i : i - 1; }
 
 // ------------------------------------------------------------------ indices
+// An index yields, for node n, the element offsets off[i] (i = 1..18) of the
+// populations pulled into n, each relative to the base of its opposite pair,
+// src + (i odd ? i : i - 1) * stride: the value leaving the node at x_n - c_i,
+// or, when that voxel is solid, the node's own opposite population (halfway
+// bounce-back).  For the adjoint it also yields boff[i], the transposed
+// offsets: the population of direction i that the node at x_n + c_i pulled
+// from n, or at a wall the one n pulled itself.
+//
+// Both indices split into load (issue the memory reads for a node) and
+// resolve (arithmetic on what was read), so a caller can overlap the reads of
+// one node with the population traffic of another.
+
+// Device table of pull offsets [18][stride] (built on the host from the
+// pull-source table, see table_to_pull_offsets).
 struct TableIdx {
     const int32_t* __restrict__ t;
-    int64_t stride;
-    struct Loc {};
-    __device__ __forceinline__ Loc locate(int64_t) const { return {}; }
-    // pull source of direction I at node n, -1 for a solid source
-    template <int I>
-    __device__ __forceinline__ int64_t src(const Loc&, int64_t n) const {
-        return t[(int64_t)(I - 1) * stride + n];
+    uint32_t stride;
+    using Pre = uint32_t;  // nothing to fetch ahead
+    __device__ __forceinline__ Pre prefetch(uint32_t) const { return 0u; }
+    struct Raw {
+        uint32_t t[19];
+    };
+    __device__ __forceinline__ void load(uint32_t n, Pre, Raw& r) const {
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            r.t[i] = (uint32_t)ld_off(t + (size_t)(i - 1) * stride, n * 4u);
+        });
+    }
+    __device__ __forceinline__ void resolve(const Raw& r, Pre, uint32_t, uint32_t off[19]) const {
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            off[i] = r.t[i];
+        });
+    }
+    // an entry is >= stride exactly when it points into the second array of
+    // the pair, so the transposed offset is the opposite entry moved across
+    __device__ __forceinline__ void transpose(const Raw& r, Pre, uint32_t, uint32_t boff[19]) const {
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            const uint32_t o = r.t[opp(i)];
+            boff[i] = o >= stride ? o - stride : o + stride;
+        });
     }
 };
 
+// Row-word records of the padded bit strings built on the host: 32 padded
+// positions per 16-byte record {bits, base, count, 0}; position x + 1 is
+// voxel x and the two ends repeat the opposite voxel (periodic x).
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
-    const uint64_t* __restrict__ rowbits;
-    const int32_t* __restrict__ wordbase;
-    int nx, ny, nz, W, bx, by;
-    struct Loc {
-        int x, y, z;
+    const uint4* __restrict__ rec;
+    uint32_t nx, ny, nz, R, bx, by, stride;
+
+    struct RowRaw {
+        uint32_t bits, base, count, next;  // record of word x >> 5, low bits of the next
     };
-    __device__ __forceinline__ Loc locate(int64_t n) const {
-        const uint32_t c = coords[n];
-        Loc l;
-        l.x = (int)(c & ((1u << bx) - 1u));
-        l.y = (int)((c >> bx) & ((1u << by) - 1u));
-        l.z = (int)((uint64_t)c >> (bx + by));
-        return l;
+    __device__ __forceinline__ RowRaw row_at(uint32_t off) const {
+        const uint4 a = ld_off(rec, off);
+        RowRaw w;
+        w.bits = a.x;
+        w.base = a.y;
+        w.count = a.z;
+        w.next = ld_off(reinterpret_cast<const uint32_t*>(rec), off + 16u);
+        return w;
     }
-    template <int I>
-    __device__ __forceinline__ int64_t src(const Loc& l, int64_t) const {
-        constexpr int cx = cdir(I, 0), cy = cdir(I, 1), cz = cdir(I, 2);
-        int xs = l.x - cx, ys = l.y - cy, zs = l.z - cz;
-        if (cx > 0 && xs < 0) xs += nx;
-        if (cx < 0 && xs >= nx) xs -= nx;
-        if (cy > 0 && ys < 0) ys += ny;
-        if (cy < 0 && ys >= ny) ys -= ny;
-        if (cz > 0 && zs < 0) zs += nz;
-        if (cz < 0 && zs >= nz) zs -= nz;
-        const int64_t wi = ((int64_t)zs * ny + ys) * W + (xs >> 6);
-        const uint64_t bits = rowbits[wi];
-        const int b = xs & 63;
-        const int32_t base = wordbase[wi];
-        const int64_t idx = base + __popcll(bits & ((1ull << b) - 1ull));
-        return ((bits >> b) & 1ull) ? idx : (int64_t)-1;
+    // voxels x - 1, x, x + 1 of a row: fluid bits (bit 0..2) and node numbers
+    struct Row3 {
+        int32_t rm, r0, rp;
+        uint32_t bits;
+    };
+    __device__ __forceinline__ Row3 decode(const RowRaw& w, uint32_t x, bool x_first, bool x_last) const {
+        const uint32_t sh = x & 31u;
+        Row3 r;
+        r.bits = __builtin_amdgcn_alignbit(w.next, w.bits, sh) & 7u;   // padded positions x..x+2
+        const int32_t below = (int32_t)__popc(__builtin_amdgcn_ubfe(w.bits, 0u, sh));
+        r.r0 = (int32_t)w.base + below + (int32_t)(r.bits & 1u);
+        r.rm = r.r0 - 1 + (x_first ? (int32_t)w.count : 0);
+        r.rp = r.r0 + (int32_t)((r.bits >> 1) & 1u) - (x_last ? (int32_t)w.count : 0);
+        return r;
+    }
+    using Pre = uint32_t;  // the node's packed coordinate, loaded ahead of use
+    __device__ __forceinline__ Pre prefetch(uint32_t n) const { return ld_off(coords, n * 4u); }
+    struct Raw {
+        RowRaw own, ym, yp, zm, zp, mm, pp, mp, pm;
+    };
+    // issue the nine row-record loads of the node with packed coordinate c
+    __device__ __forceinline__ void load(uint32_t, Pre c, Raw& r) const {
+        const uint32_t x = c & ((1u << bx) - 1u);
+        const uint32_t y = (c >> bx) & ((1u << by) - 1u);
+        const uint32_t z = (uint32_t)((uint64_t)c >> (bx + by));
+        const uint32_t rowb = R * 16u, planeb = ny * rowb;
+        const uint32_t o = ((z * ny + y) * R + (x >> 5)) * 16u;
+        // byte steps to the rows y - 1, y + 1, z - 1, z + 1 (periodic)
+        const uint32_t dym = y == 0 ? (ny - 1) * rowb : 0u - rowb;
+        const uint32_t dyp = y == ny - 1 ? 0u - (ny - 1) * rowb : rowb;
+        const uint32_t dzm = z == 0 ? (nz - 1) * planeb : 0u - planeb;
+        const uint32_t dzp = z == nz - 1 ? 0u - (nz - 1) * planeb : planeb;
+        const uint32_t o1 = o + dym, o2 = o + dyp, o3 = o + dzm, o4 = o + dzp, o5 = o3 + dym,
+                       o6 = o4 + dyp, o7 = o4 + dym, o8 = o3 + dyp;
+        // all addresses first, then the loads back to back
+        __builtin_amdgcn_sched_barrier(0);
+        r.own = row_at(o);
+        r.ym = row_at(o1);
+        r.yp = row_at(o2);
+        r.zm = row_at(o3);
+        r.zp = row_at(o4);
+        r.mm = row_at(o5);
+        r.pp = row_at(o6);
+        r.mp = row_at(o7);
+        r.pm = row_at(o8);
+    }
+    // pull sources s[i] (node number or -1) from the decoded rows
+    __device__ __forceinline__ void sources(const Raw& r, Pre c, int32_t s[19]) const {
+        const uint32_t x = c & ((1u << bx) - 1u);
+        const bool xf = x == 0, xl = x == nx - 1;
+        auto pick = [](const Row3& w, int which) -> int32_t {
+            const uint32_t bit = (w.bits >> (which + 1)) & 1u;
+            const int32_t v = which < 0 ? w.rm : (which == 0 ? w.r0 : w.rp);
+            return bit ? v : -1;
+        };
+        // source x' = x - c_x: c_x = +1 reads x - 1 (which -1), c_x = -1 reads x + 1
+        const Row3 o = decode(r.own, x, xf, xl);
+        s[1] = pick(o, -1);
+        s[2] = pick(o, +1);
+        const Row3 a = decode(r.ym, x, xf, xl);   // c_y = +1
+        s[3] = pick(a, 0);
+        s[7] = pick(a, -1);
+        s[10] = pick(a, +1);
+        const Row3 b = decode(r.yp, x, xf, xl);   // c_y = -1
+        s[4] = pick(b, 0);
+        s[8] = pick(b, +1);
+        s[9] = pick(b, -1);
+        const Row3 d = decode(r.zm, x, xf, xl);   // c_z = +1
+        s[5] = pick(d, 0);
+        s[11] = pick(d, -1);
+        s[14] = pick(d, +1);
+        const Row3 e = decode(r.zp, x, xf, xl);   // c_z = -1
+        s[6] = pick(e, 0);
+        s[12] = pick(e, +1);
+        s[13] = pick(e, -1);
+        s[15] = pick(decode(r.mm, x, xf, xl), 0);
+        s[16] = pick(decode(r.pp, x, xf, xl), 0);
+        s[17] = pick(decode(r.mp, x, xf, xl), 0);
+        s[18] = pick(decode(r.pm, x, xf, xl), 0);
+    }
+    __device__ __forceinline__ void resolve(const Raw& r, Pre c, uint32_t n, uint32_t off[19]) const {
+        int32_t s[19];
+        sources(r, c, s);
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            off[i] = pull_offset(i, s[i], n, stride);
+        });
+    }
+    __device__ __forceinline__ void transpose(const Raw& r, Pre c, uint32_t n, uint32_t boff[19]) const {
+        int32_t s[19];
+        sources(r, c, s);
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            boff[i] = pull_offset(i, s[opp(i)], n, stride);
+        });
     }
 };
 
@@ -262,15 +401,12 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
     }
 }
 
-// Node range of a block: fixed contiguous chunks of 256 nodes, with logical
-// block ids remapped so that each XCD owns a contiguous part of the list
-// (neighbouring rows then share that XCD's L2).
-__device__ __forceinline__ void block_range(int64_t nf, int& lb, int64_t& c0, int64_t& c1) {
-    const int G = gridDim.x, b = blockIdx.x;
-    lb = (G % kXcds == 0) ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
-    const int64_t chunks = (nf + kThreads - 1) / kThreads;
-    c0 = chunks * lb / G;
-    c1 = chunks * (lb + 1) / G;
+// Logical block id: hardware block b runs on XCD b % 8; remapping gives each
+// XCD a contiguous run of logical ids, so chunk c (processed by logical block
+// c % gridDim.x) and its neighbouring chunks share that XCD's L2.
+__device__ __forceinline__ uint32_t logical_block() {
+    const uint32_t G = gridDim.x, b = blockIdx.x;
+    return (G % kXcds == 0) ? (b % kXcds) * (G / kXcds) + b / kXcds : b;
 }
 
 // Fixed-order FP64 sum of per-block partials [grid][K] into out[0..K-1], by
@@ -297,50 +433,90 @@ k_finalize(const double* __restrict__ partials, int grid, double* __restrict__ o
 template <class C, class Ix, bool FIELD>
 __global__ void __launch_bounds__(kThreads)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
-       int64_t stride, int64_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
+       uint32_t stride, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
        const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
        const double* __restrict__ prev_partials, double* __restrict__ prev_out) {
+    using T = typename C::T;
     // The previous step's block partials are reduced here, by the first block,
     // so a time step is a single launch; kernel order makes them visible.
     if (prev_out != nullptr && blockIdx.x == 0) {
         reduce_partials<4>(prev_partials, gridDim.x, prev_out);
         __syncthreads();
     }
-    int lb;
-    int64_t c0, c1;
-    block_range(nf, lb, c0, c1);
+    const uint32_t lb = logical_block();
+    const uint32_t chunks = (nf + kThreads - 1) / kThreads;
+    const uint32_t G = gridDim.x;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t c = c0; c < c1; ++c) {
-        const int64_t n = c * kThreads + threadIdx.x;
-        if (n >= nf) continue;
-        const auto loc = ix.locate(n);
-        float f[19];
-        f[0] = C::ld(src, n, inv);
-        unroll<18>([&](auto k) {
-            constexpr int i = decltype(k)::value + 1;
-            const int64_t s = ix.template src<i>(loc, n);
-            const int64_t a = s >= 0 ? (int64_t)i * stride + s : (int64_t)opp(i) * stride + n;
-            f[i] = C::ld(src, a, inv);
-        });
-        float Fx = Fx0, Fy = Fy0, Fz = Fz0;
-        if (FIELD) {
-            Fx = field[n];
-            Fy = field[nf + n];
-            Fz = field[2 * nf + n];
+    // Software pipeline over this block's chunks c, c + G, c + 2G, ...: while
+    // the populations of node n are gathered, the neighbour index of the next
+    // node n1 is resolved and the coordinate of the one after (n2) is
+    // fetched, so each iteration waits for memory once.  Node numbers past
+    // the list are clamped to the last node for loads and never stored.
+    auto node_of = [&](uint32_t cc) { return min(cc * kThreads + threadIdx.x, nf - 1); };
+    uint32_t c = lb;
+    if (c < chunks) {
+        uint32_t n = node_of(c), n1 = node_of(c + G);
+        typename Ix::Pre pre1 = ix.prefetch(n1);
+        uint32_t off[19];
+        {
+            const typename Ix::Pre p0 = ix.prefetch(n);
+            typename Ix::Raw raw;
+            ix.load(n, p0, raw);
+            ix.resolve(raw, p0, n, off);
         }
-        const Mom m = moments(f);
-        const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
-        acc[0] += (double)jx;
-        acc[1] += (double)jy;
-        acc[2] += (double)jz;
-        acc[3] += (double)m.rho;
-        add_back(f, collide_increment(m, jx, jy, jz, Fx, Fy, Fz, r));
-        unroll<19>([&](auto k) {
-            constexpr int i = decltype(k)::value;
-            C::st(dst, (int64_t)i * stride + n, f[i], scale);
-        });
+        for (;;) {
+            // (1) index loads of the next node, (2) population loads of this
+            // node and the coordinate two nodes ahead, (3) decode the index
+            // while the populations are in flight, (4) collide and store.
+            __builtin_amdgcn_sched_barrier(0);
+            typename Ix::Raw raw;
+            ix.load(n1, pre1, raw);
+            __builtin_amdgcn_sched_barrier(0);
+            T fr[19];
+            fr[0] = ld_off(src, n * (uint32_t)sizeof(T));
+            unroll<18>([&](auto k) {
+                constexpr int i = decltype(k)::value + 1;
+                fr[i] = ld_off(src + (size_t)pair_first(i) * stride, off[i] * (uint32_t)sizeof(T));
+            });
+            const typename Ix::Pre pre2 = ix.prefetch(node_of(c + 2 * G));
+            __builtin_amdgcn_sched_barrier(0);
+            ix.resolve(raw, pre1, n1, off);
+            __builtin_amdgcn_sched_barrier(0);
+            float f[19];
+            unroll<19>([&](auto k) {
+                constexpr int i = decltype(k)::value;
+                f[i] = C::cvt(fr[i], inv);
+            });
+            float Fx = Fx0, Fy = Fy0, Fz = Fz0;
+            if (FIELD) {
+                Fx = field[n];
+                Fy = field[nf + n];
+                Fz = field[2 * nf + n];
+            }
+            const Mom m = moments(f);
+            const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
+            add_back(f, collide_increment(m, jx, jy, jz, Fx, Fy, Fz, r));
+            // Lanes past the list carry n = nf - 1: they recompute that node
+            // from the same inputs and store the same values, so the stores
+            // stay unconditional (no branch for the compiler to sink the
+            // gathers into); only the reduction masks them out.
+            const double live = (c * kThreads + threadIdx.x < nf) ? 1.0 : 0.0;
+            acc[0] += live * (double)jx;
+            acc[1] += live * (double)jy;
+            acc[2] += live * (double)jz;
+            acc[3] += live * (double)m.rho;
+            unroll<19>([&](auto k) {
+                constexpr int i = decltype(k)::value;
+                st_stream(dst + (size_t)i * stride, n * (uint32_t)sizeof(T), C::enc(f[i], scale));
+            });
+            c += G;
+            if (c >= chunks) break;
+            n = n1;
+            n1 = node_of(c + G);
+            pre1 = pre2;
+        }
     }
-    block_sum<4>(acc, partials + (int64_t)lb * 4);
+    block_sum<4>(acc, partials + (size_t)lb * 4);
 }
 
 __global__ void k_zero(uint32_t* p, int64_t words) {
@@ -353,7 +529,7 @@ template <class C>
 __global__ void k_rescale(typename C::T* p, int64_t count, float factor) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x)
-        C::st(p, i, C::ld(p, i, 1.f), factor);
+        p[i] = C::enc(C::cvt(p[i], 1.f), factor);
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -381,26 +557,30 @@ __device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w
 template <class Ix, bool FIELD>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* __restrict__ st,
-          Ix ix, int64_t stride, int64_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
+          Ix ix, uint32_t stride, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
           const float* __restrict__ field, double* __restrict__ dkdF, double* __restrict__ partials) {
-    int lb;
-    int64_t c0, c1;
-    block_range(nf, lb, c0, c1);
+    const uint32_t lb = logical_block();
+    const uint32_t chunks = (nf + kThreads - 1) / kThreads;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t c = c0; c < c1; ++c) {
-        const int64_t n = c * kThreads + threadIdx.x;
+    for (uint32_t c = lb; c < chunks; c += gridDim.x) {
+        const uint32_t n = c * kThreads + threadIdx.x;
         if (n >= nf) continue;
-        const auto loc = ix.locate(n);
+        uint32_t off[19], boff[19];
+        {
+            const typename Ix::Pre p0 = ix.prefetch(n);
+            typename Ix::Raw raw;
+            ix.load(n, p0, raw);
+            ix.resolve(raw, p0, n, off);
+            ix.transpose(raw, p0, n, boff);
+        }
+        __builtin_amdgcn_sched_barrier(0);
         float f[19], b[19];
-        f[0] = st[n];
-        b[0] = ain[n];
+        f[0] = ld_off(st, n * 4u);
+        b[0] = ld_off(ain, n * 4u);
         unroll<18>([&](auto k) {
             constexpr int i = decltype(k)::value + 1;
-            const int64_t s = ix.template src<i>(loc, n);
-            f[i] = st[s >= 0 ? (int64_t)i * stride + s : (int64_t)opp(i) * stride + n];
-            // adjoint of the pull: a value pulled by the node at x + c_i from x
-            const int64_t t = ix.template src<opp(i)>(loc, n);
-            b[i] = ain[t >= 0 ? (int64_t)i * stride + t : (int64_t)opp(i) * stride + n];
+            f[i] = ld_off(st + (size_t)pair_first(i) * stride, off[i] * 4u);
+            b[i] = ld_off(ain + (size_t)pair_first(i) * stride, boff[i] * 4u);
         });
         float Fx = Fx0, Fy = Fy0, Fz = Fz0;
         if (FIELD) {
@@ -491,16 +671,16 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
         const float gFz = 0.5f * nu.jz + gjd.z + tq * gq * mu.qz + mu.jz;
         dkdF[n] += (double)gFx;
         dkdF[nf + n] += (double)gFy;
-        dkdF[2 * nf + n] += (double)gFz;
+        dkdF[2 * (size_t)nf + n] += (double)gFz;
         add_back(b, nu);
         unroll<19>([&](auto k) {
             constexpr int i = decltype(k)::value;
-            aout[(int64_t)i * stride + n] = b[i];
+            st_off(aout + (size_t)i * stride, n * 4u, b[i]);
         });
     }
     double part[6];
     block_sum<6>(acc, part);
-    if ((int)threadIdx.x < 6) partials[(int64_t)lb * 6 + threadIdx.x] += part[threadIdx.x];
+    if ((int)threadIdx.x < 6) partials[(size_t)lb * 6 + threadIdx.x] += part[threadIdx.x];
 }
 
 __global__ void k_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa) {
@@ -526,9 +706,11 @@ int grid_for(int64_t n) {
     return (int)g;
 }
 
-TableIdx table_view(const IndexView& v) { return TableIdx{v.table, v.stride}; }
+TableIdx table_view(const IndexView& v) { return TableIdx{v.table, (uint32_t)v.stride}; }
 BitmapIdx bitmap_view(const IndexView& v) {
-    return BitmapIdx{v.coords, v.rowbits, v.wordbase, v.nx, v.ny, v.nz, v.W, v.bx, v.by};
+    return BitmapIdx{v.coords, static_cast<const uint4*>(v.rec), (uint32_t)v.nx, (uint32_t)v.ny,
+                     (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by,
+                     (uint32_t)v.stride};
 }
 
 template <class C, class Ix>
@@ -538,11 +720,11 @@ hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
     T* dst = static_cast<T*>(a.dst);
     if (a.field)
         hipLaunchKernelGGL((k_step<C, Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
-                           a.idx.stride, a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
+                           (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
                            a.inv_scale, a.partials, a.prev_partials, a.prev_out);
     else
         hipLaunchKernelGGL((k_step<C, Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
-                           ix, a.idx.stride, a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
+                           ix, (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
                            a.scale, a.inv_scale, a.partials, a.prev_partials, a.prev_out);
     return hipGetLastError();
 }
@@ -557,12 +739,12 @@ template <class Ix>
 hipError_t adjoint_with(const AdjLaunch& a, Ix ix, hipStream_t s) {
     if (a.field)
         hipLaunchKernelGGL((k_adjoint<Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
-                           a.adj_out, a.state, ix, a.idx.stride, a.nf, a.rates, a.F[0], a.F[1],
-                           a.F[2], a.field, a.dk_dF, a.partials);
+                           a.adj_out, a.state, ix, (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates,
+                           a.F[0], a.F[1], a.F[2], a.field, a.dk_dF, a.partials);
     else
         hipLaunchKernelGGL((k_adjoint<Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
-                           a.adj_out, a.state, ix, a.idx.stride, a.nf, a.rates, a.F[0], a.F[1],
-                           a.F[2], nullptr, a.dk_dF, a.partials);
+                           a.adj_out, a.state, ix, (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates,
+                           a.F[0], a.F[1], a.F[2], nullptr, a.dk_dF, a.partials);
     return hipGetLastError();
 }
 
@@ -575,6 +757,22 @@ hipError_t launch_step(const StepLaunch& a, hipStream_t s) {
         case kBF16: return step_codec<CodecBF16>(a, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t step_occupancy(int storage, int index_kind, int* blocks_per_cu) {
+    auto q = [&](const void* k) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kThreads, 0);
+    };
+#define LBM_OCC(C, I) q(reinterpret_cast<const void*>(&k_step<C, I, false>))
+    if (index_kind == kTable) {
+        if (storage == kF32) return LBM_OCC(CodecF32, TableIdx);
+        if (storage == kF16) return LBM_OCC(CodecF16, TableIdx);
+        return LBM_OCC(CodecBF16, TableIdx);
+    }
+    if (storage == kF32) return LBM_OCC(CodecF32, BitmapIdx);
+    if (storage == kF16) return LBM_OCC(CodecF16, BitmapIdx);
+    return LBM_OCC(CodecBF16, BitmapIdx);
+#undef LBM_OCC
 }
 
 hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s) {

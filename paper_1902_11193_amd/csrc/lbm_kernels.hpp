@@ -20,10 +20,9 @@ struct IndexView {
     int kind;
     int64_t stride;             // padded node count (row stride of [19][np] arrays)
     const int32_t* table;       // kTable: [18][stride]
-    const uint32_t* coords;     // kBitmap: [nf]
-    const uint64_t* rowbits;    // kBitmap: [ny*nz*W]
-    const int32_t* wordbase;    // kBitmap: [ny*nz*W]
-    int nx, ny, nz, W, bx, by;  // kBitmap geometry
+    const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
+    const void* rec;            // kBitmap: [ny*nz*R] 16-byte row-word records
+    int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = records per row
 };
 
 struct StepLaunch {
@@ -45,6 +44,9 @@ struct StepLaunch {
 // One fused step: gather with halfway bounce-back, MRT + Guo collision, store,
 // and per-block FP64 partial sums of (ux, uy, uz, drho).
 hipError_t launch_step(const StepLaunch& a, hipStream_t s);
+
+// Resident blocks per compute unit of the step kernel for this storage/index.
+hipError_t step_occupancy(int storage, int index_kind, int* blocks_per_cu);
 
 // Sum the per-block partials in fixed order into out[0..3].
 hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s);

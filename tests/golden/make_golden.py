@@ -1,10 +1,14 @@
-"""Writes tests/golden/sc_sphere_32.json with the FP64 oracle only.
+"""Writes golden values of the FP64 oracle (and nothing else) under tests/golden/.
 
+sc_sphere_32.json:
 The 32^3 periodic box with one solid sphere of radius 8 voxels (simple-cubic
 array), g = (1e-6, 0, 0), tau = 1, Set E with Lambda = 3/16: the per-step
 mean velocity is recorded and the run stops when the per-step relative change
 of <u_x> falls below 1e-9 or after 5000 steps.
-Run: python tests/golden/make_golden.py
+grf_crop128.json: the 128^3 corner crop (re-filtered for x-spanning fluid) of
+the 512^3 Gaussian-random-field rock of porosity 0.2, tau = 1, Set E,
+Lambda = 3/16, g = (1e-6, 0, 0); <u_x> after 500, 1000 and 2000 steps.
+Run: python tests/golden/make_golden.py [sc_sphere_32|grf_crop128]
 """
 import json
 import os
@@ -15,7 +19,31 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import oracle as O  # noqa: E402
-from lbm_inputs import workload  # noqa: E402
+from lbm_inputs import crop, workload  # noqa: E402
+
+
+def grf_crop128():
+    m = crop(workload("grf_512"), 128)
+    p = O.Problem(m, 1.0, 3 / 16, "E", (1e-6, 0.0, 0.0))
+    fh = p.initial()
+    marks = (500, 1000, 2000)
+    out = {}
+    t0 = time.time()
+    for n in range(1, marks[-1] + 1):
+        fh, u = p.step(fh)
+        if n in marks:
+            out[str(n)] = float(p.mean_velocity(u)[0])
+            print(n, out[str(n)], time.time() - t0, flush=True)
+    res = dict(
+        about="FP64 oracle, 128^3 corner crop of the grf_512 workload (x-spanning fluid kept), tau=1, "
+              "Set E Lambda=3/16, g=(1e-6,0,0); written by tests/golden/make_golden.py",
+        n_fluid=int((m == 0).sum()),
+        umean_x=out,
+    )
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grf_crop128.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
 
 
 def main():
@@ -53,4 +81,5 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    which = sys.argv[1] if len(sys.argv) > 1 else "sc_sphere_32"
+    {"sc_sphere_32": main, "grf_crop128": grf_crop128}[which]()

@@ -22,19 +22,33 @@ def oracle_problem(mask, tau, Lam, rset, g, linear=False):
     return O.Problem(mask, tau, Lam, rset, g, linear=linear)
 
 
+def _perm(problem):
+    """Raster position (among fluid voxels) of every library node."""
+    if not hasattr(problem, "_lib_perm"):
+        problem._lib_perm = P.raster_permutation(problem.solid.numpy().astype(np.uint8))
+    return problem._lib_perm
+
+
 def dense_from_lib(problem, f_lib):
-    """Library state (19, nf) in library order -> oracle dense (19, nz, ny, nx)."""
+    """Library state (19, nf): library velocity and node order -> oracle dense (19, nz, ny, nx)."""
+    raster = np.empty_like(f_lib)
+    raster[:, _perm(problem)] = f_lib
     fh = torch.zeros((19,) + problem.shape, dtype=torch.float64)
-    fh[:, problem.fluid] = torch.from_numpy(f_lib[PERM])
+    fh[:, problem.fluid] = torch.from_numpy(raster[PERM])
     return fh
 
 
 def lib_from_dense(problem, fh):
-    """Oracle dense state -> (19, nf) in library order."""
+    """Oracle dense state -> (19, nf) in library velocity and node order."""
     f_orc = fh[:, problem.fluid].numpy()
     out = np.empty_like(f_orc)
     out[PERM] = f_orc
-    return out
+    return out[:, _perm(problem)]
+
+
+def nodes_from_raster(mask, a):
+    """Per-fluid-voxel array (..., nf) in raster order -> library node order."""
+    return a[..., P.raster_permutation(mask)]
 
 
 def random_state(nf, seed, amp=1e-3):

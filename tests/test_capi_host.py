@@ -67,10 +67,19 @@ def test_rates_reject():
         assert e.value.code == P.LBM_EINVAL
 
 
+def _brute_node_order(mask, tile=16):
+    """Fluid voxels sorted by (z // tile, y, z % tile, x)."""
+    nz, ny, nx = mask.shape
+    fl = np.flatnonzero(mask.reshape(-1) == 0)
+    z, y, x = np.unravel_index(fl, mask.shape)
+    key = np.lexsort((x, z % tile, y, z // tile))
+    return fl[key]
+
+
 def _brute_table(mask):
     nz, ny, nx = mask.shape
     c = P.lbm_velocities()
-    fl = np.flatnonzero(mask.reshape(-1) == 0)
+    fl = _brute_node_order(mask)
     node = -np.ones(mask.size, np.int64)
     node[fl] = np.arange(len(fl))
     z, y, x = np.unravel_index(fl, mask.shape)
@@ -100,6 +109,16 @@ def test_neighbor_table_brute_force_and_permutation(shape, sf, seed):
         np.add.at(reads[i], src[ok], 1)
         np.add.at(reads[j], np.flatnonzero(~ok), 1)
     assert (reads == 1).all()
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (40, 3, 9), (33, 17, 2)])
+def test_node_order_is_z_tiled_rows(shape):
+    mask = random_mask(shape, 0.3, 4)
+    order = P.lbm_node_order(mask)
+    assert np.array_equal(order, _brute_node_order(mask))
+    assert np.array_equal(np.sort(order), np.flatnonzero(mask.reshape(-1) == 0))
+    perm = P.raster_permutation(mask)
+    assert np.array_equal(np.flatnonzero(mask.reshape(-1) == 0)[perm], order)
 
 
 def test_workspace_query_counts_and_errors():

@@ -10,7 +10,7 @@ import torch
 
 import oracle as O
 import paper_1902_11193_amd as P
-from gpu_helpers import banner
+from gpu_helpers import banner, nodes_from_raster
 from lbm_inputs import random_mask, percolating_x, workload, crop
 
 pytestmark = pytest.mark.gpu
@@ -31,7 +31,7 @@ def _compare(mask, rset, tau, Lam, g, N, K, index="bitmap"):
     else:
         assert r["dk_dLambda"] == 0.0
     dg = r["dk_dg"].cpu().numpy()
-    og = o["dk_dg"].numpy()
+    og = nodes_from_raster(mask, o["dk_dg"].numpy())
     scale = np.abs(og).max()
     assert np.abs(dg - og).max() < 1e-4 * scale, np.abs(dg - og).max() / scale
     return r, o
@@ -83,7 +83,9 @@ def test_autograd_function_matches_solver_adjoint():
     gfield.requires_grad_(True)
     k = P.permeability(mask, tau, lam, gfield, "E", (1e-5, 0, 0), n_steps=60, checkpoint_every=16)
     k.backward()
-    assert abs(k.item() / ref["k"] - 1) < 1e-12
-    assert abs(tau.grad.item() - ref["dk_dtau"]) <= 1e-12 * abs(ref["dk_dtau"]) + 1e-300
-    assert abs(lam.grad.item() - ref["dk_dLambda"]) <= 1e-12 * abs(ref["dk_dLambda"])
-    assert torch.allclose(gfield.grad, ref["dk_dg"].float())
+    # the autograd path runs the per-node force kernels: equal up to FP32 rounding
+    assert abs(k.item() / ref["k"] - 1) < 1e-6
+    assert abs(tau.grad.item() - ref["dk_dtau"]) <= 1e-5 * max(abs(ref["dk_dtau"]), ref["k"])
+    assert abs(lam.grad.item() - ref["dk_dLambda"]) <= 1e-5 * max(abs(ref["dk_dLambda"]), ref["k"])
+    scale = ref["dk_dg"].abs().max().item()
+    assert (gfield.grad.double() - ref["dk_dg"]).abs().max().item() < 1e-5 * scale
