@@ -133,9 +133,11 @@ def main():
     ap.add_argument("--g", type=float, default=None)
     ap.add_argument("--adj-steps", type=int, default=100)
     ap.add_argument("--adj-checkpoint", type=int, default=10)
-    ap.add_argument("--cpu-crop", type=int, default=96)
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--cpu-crop", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device (a kernel of known traffic for counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -157,6 +159,13 @@ def main():
     print(f"[bench] {args.workload}: generated in {gen_s:.1f}s, porosity {porosity(mask):.4f}", file=sys.stderr,
           flush=True)
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
 
     main_r = run_forward(P, mask, args, "f32")
     print(f"[bench] f32 {main_r['MFLUPS']:.0f} MFLUPS {main_r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
