@@ -1,5 +1,5 @@
 // C-ABI of liblbm (declarations and contracts in include/lbm.h).
-#include "../../include/lbm.h"
+#include "lbm.h"
 
 #include <hip/hip_runtime_api.h>
 
