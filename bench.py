@@ -106,6 +106,36 @@ def run_adjoint(P, mask, args):
                 MFLUPS_equivalent=nf * N / t / 1e6)
 
 
+def run_steady(P, mask, args, storage):
+    """Run to the paper's steady-state criterion (per-step relative change of
+    k below eps) in segments, printing progress; reports steps, k and rate."""
+    import torch
+
+    s = P.Solver(mask, args.tau, args.Lambda, "E", (args.g, 0.0, 0.0), storage, args.index)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, conv, k = 0, False, float("nan")
+    while done < args.max_steps and not conv:
+        r = s.run_to_steady(eps=args.eps, check_every=100, max_steps=min(2000, args.max_steps - done))
+        done += r["steps"]
+        conv, k = r["converged"], float(r["k"][0])
+        print(f"[bench] steady {storage}: {done} steps, k = {k:.9g}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    # The per-step test can also be met where k turns (an acoustic overshoot);
+    # stepping on shows how far k still moves after the criterion first holds.
+    s.step(args.steady_extra)
+    k_extra = float(s.permeability()[0])
+    print(f"[bench] steady {storage}: +{args.steady_extra} steps, k = {k_extra:.9g}", file=sys.stderr, flush=True)
+    nf = s.n_fluid
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return dict(storage=storage, steps=done, converged=conv, k=k, seconds=t, MFLUPS=nf * done / t / 1e6,
+                eps=args.eps, extra_steps=args.steady_extra, k_after_extra=k_extra,
+                k_drift_after_extra=k_extra / k - 1)
+
+
 def cpu_baseline(mask_full, crop_n: int, steps: int):
     import torch
 
@@ -136,6 +166,11 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--steady", action="store_true",
+                    help="also run FP32 and FP16 storage to steady state and compare k")
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--max-steps", type=int, default=30000)
+    ap.add_argument("--steady-extra", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter calibration)")
     args = ap.parse_args()
@@ -154,7 +189,7 @@ def main():
     if args.g is None:
         args.g = w["g"]
     t0 = time.time()
-    mask = workload(args.workload)
+    mask = workload(args.workload, verbose=True)
     gen_s = time.time() - t0
     print(f"[bench] {args.workload}: generated in {gen_s:.1f}s, porosity {porosity(mask):.4f}", file=sys.stderr,
           flush=True)
@@ -177,6 +212,12 @@ def main():
         elif v == "adjoint":
             variants["adjoint"] = run_adjoint(P, mask, args)
         print(f"[bench] {v} done", file=sys.stderr, flush=True)
+
+    steady = None
+    if args.steady:
+        steady = {st: run_steady(P, mask, args, st) for st in ("f32", "f16")}
+        steady["k_rel_f16_vs_f32"] = steady["f16"]["k"] / steady["f32"]["k"] - 1
+        steady["k_rel_f16_vs_f32_after_extra"] = steady["f16"]["k_after_extra"] / steady["f32"]["k_after_extra"] - 1
 
     nf = int((mask == 0).sum())
     alg_per_launch = ALG_BYTES["f32"] * nf
@@ -209,6 +250,8 @@ def main():
         "f32": main_r,
         "variants": variants,
     }
+    if steady is not None:
+        out["steady"] = steady
     print(json.dumps(out))
 
 
