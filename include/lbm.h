@@ -16,8 +16,10 @@
  *     solid.  The box is periodic in all three axes.
  *   - Only fluid voxels carry populations.  They are numbered 0..n_fluid-1,
  *     the "compacted fluid list", in node order: the (y, z) rows of the image
- *     taken in z-tiles of 16 planes (tile z / 16, then y, then z inside the
- *     tile), the fluid voxels of each row in increasing x.  Every per-node
+ *     taken in z-tiles of 16 planes (tile, then y, then z inside the tile),
+ *     the fluid voxels of each row in increasing x.  The T = ceil(nz / 16)
+ *     tiles come folded, t = 0, T-1, 1, T-2, ..., so tiles that touch in z
+ *     (periodic wrap included) are near each other in the list.  Every per-node
  *     array of this interface (state, force field, gradients, neighbour
  *     table) uses this order; lbm_node_order gives the voxel of each node.
  *   - Velocity order i = 0..18 (pairs i, i+1 for odd i are opposite):
@@ -59,7 +61,7 @@ extern "C" {
 #define LBM_EWORKSPACE (-3) /* workspace missing, too small or misaligned (needs 256-byte alignment) */
 #define LBM_EHIP (-4)       /* a HIP runtime call failed; message has the HIP error string */
 #define LBM_ENAN (-5)       /* non-finite mean velocity or mass: the run diverged or overflowed */
-#define LBM_ERANGE (-6)     /* image too large for the chosen index layout */
+#define LBM_ERANGE (-6)     /* image too large for the index or gather layout */
 
 /* Relaxation-rate sets of Table 2 (Sec. 2.1.3). */
 #define LBM_SRT 0
@@ -100,7 +102,11 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
               double ds_dtau[19], double ds_dLambda[19]);
 
 /* Host only.  Counts fluid voxels and the device workspace the context
- * needs.  Fails with LBM_ENOFLUID / LBM_ERANGE / LBM_EINVAL as lbm_setup. */
+ * needs.  Fails with LBM_ENOFLUID / LBM_ERANGE / LBM_EINVAL as lbm_setup.
+ * LBM_ERANGE: 2^31 or more fluid nodes; packed coordinates over 32 bits
+ * (bitmap index); or the populations gathered around one 256-node chunk
+ * spanning 4 GiB or more in the chosen storage (three 16-plane z-tiles of
+ * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16). */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
 

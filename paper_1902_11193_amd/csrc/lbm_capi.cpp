@@ -84,6 +84,15 @@ std::string check_common(const uint8_t* geom, int nx, int ny, int nz, int storag
     return "";
 }
 
+// The gathers of a chunk are 32-bit byte offsets from one base (gather_span).
+std::string check_span(const lbm::GatherSpan& g, int storage) {
+    const double bytes = (double)(g.slack + g.reach) * (double)elem_size(storage);
+    if (bytes >= 4294967296.0 || g.slack >= ((int64_t)1 << 32))
+        return "the image is too large for 32-bit gather offsets (" + std::to_string((int64_t)bytes) +
+               " bytes around a chunk); use a smaller image or 16-bit storage";
+    return "";
+}
+
 // FP16 / BF16 host encoders (round to nearest even).
 uint16_t to_bf16(float v) {
     uint32_t u;
@@ -113,6 +122,7 @@ struct lbm_ctx {
     char* ws;
     size_t ws_bytes;
     Layout L;
+    lbm::GatherSpan span;
     void* cur;   // state after the last step
     void* nxt;
     lbm::IndexView idx;
@@ -231,6 +241,8 @@ int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int sto
     if (nf >= ((int64_t)1 << 31) - 256) return fail(LBM_ERANGE, "more than 2^31 fluid nodes");
     if (index_kind == LBM_INDEX_BITMAP && !lbm::coord_bits(nx, ny, nz).fits())
         return fail(LBM_ERANGE, "packed voxel coordinates need more than 32 bits");
+    e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz), storage);
+    if (!e.empty()) return fail(LBM_ERANGE, e);
     if (bytes) *bytes = layout(lbm::padded(nf), nf, storage, index_kind, nx, ny, nz).total;
     return LBM_OK;
 }
@@ -312,6 +324,7 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     c->steps = 0;
     c->field = nullptr;
     c->geom.assign(geometry, geometry + (size_t)nx * ny * nz);
+    c->span = lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz);
     double gmax = std::max({std::fabs(g[0]), std::fabs(g[1]), std::fabs(g[2])});
     c->exponent = (storage == LBM_F16 && gmax > 0) ? (int)std::lround(-std::log2(gmax)) - 4 : 0;
     if (c->exponent < 0) c->exponent = 0;
@@ -337,12 +350,12 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     lbm::IndexView& v = c->idx;
     v.kind = index_kind;
     v.stride = c->np;
+    v.slack = c->span.slack;
     std::vector<int32_t> table;
     lbm::BitmapIndex bm;
     if (index_kind == LBM_INDEX_TABLE) {
         table.assign((size_t)18 * c->np, -1);
         lbm::build_table(geometry, nx, ny, nz, nf, c->np, table.data());
-        lbm::table_to_pull_offsets(table.data(), nf, c->np);
         v.table = reinterpret_cast<const int32_t*>(c->ws + c->L.table);
         he = hipMemcpyAsync(c->ws + c->L.table, table.data(), table.size() * 4,
                             hipMemcpyHostToDevice, c->stream);
@@ -475,7 +488,7 @@ int lbm_get_state(lbm_ctx* c, double* f) {
     for (int i = 0; i < 19; ++i) {
         const double w = weight(i);
         for (int64_t n = 0; n < c->nf; ++n) {
-            const size_t at = (size_t)i * c->np + n;
+            const size_t at = (size_t)lbm::state_elem(i, n);
             double d;
             if (c->storage == LBM_F32)
                 d = reinterpret_cast<const float*>(raw.data())[at];
@@ -497,7 +510,7 @@ int lbm_set_state(lbm_ctx* c, const double* f) {
     for (int i = 0; i < 19; ++i) {
         const double w = weight(i);
         for (int64_t n = 0; n < c->nf; ++n) {
-            const size_t at = (size_t)i * c->np + n;
+            const size_t at = (size_t)lbm::state_elem(i, n);
             const double d = f[(size_t)i * c->nf + n] - w;
             if (c->storage == LBM_F32)
                 reinterpret_cast<float*>(raw.data())[at] = (float)d;
@@ -613,7 +626,7 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
     // reverse sweep
     float* a_in = (float*)(ws + A.adjA);
     float* a_out = (float*)(ws + A.adjB);
-    HIP_TRY(lbm::launch_adjoint_seed(a_in, c->np, c->nf, c->axis, (float)(nu / (gref * V)), c->stream));
+    HIP_TRY(lbm::launch_adjoint_seed(a_in, c->nf, c->axis, (float)(nu / (gref * V)), c->stream));
     HIP_TRY(lbm::launch_zero(part6, (int64_t)kMaxGrid * 6 * 8, c->stream));
     HIP_TRY(lbm::launch_zero(dk_dg, (int64_t)3 * c->nf * 8, c->stream));
     lbm::AdjLaunch al{};

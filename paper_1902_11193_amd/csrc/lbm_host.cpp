@@ -4,6 +4,7 @@
 #include "lbm_host.hpp"
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <thread>
 
@@ -148,15 +149,45 @@ std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
             }
     });
     int64_t n = 0;
-    for (int z0 = 0; z0 < nz; z0 += kNodeTileZ)
+    const int T = (nz + kNodeTileZ - 1) / kNodeTileZ;
+    for (int p = 0; p < T; ++p) {
+        const int z0 = tile_at(p, T) * kNodeTileZ;
         for (int y = 0; y < ny; ++y)
             for (int z = z0; z < std::min(nz, z0 + kNodeTileZ); ++z) {
                 const int64_t r = (int64_t)z * ny + y;
                 start[r] = n;
                 n += cnt[r];
             }
+    }
     start[rows] = n;
     return start;
+}
+
+GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz) {
+    const int T = (nz + kNodeTileZ - 1) / kNodeTileZ;
+    const int64_t total = start[(int64_t)ny * nz];
+    // first node of the tile at each position, and one past its last
+    std::vector<int64_t> first(T), last(T);
+    for (int p = 0; p < T; ++p) first[p] = start[(int64_t)tile_at(p, T) * kNodeTileZ * ny];
+    for (int p = 0; p < T; ++p) last[p] = p + 1 < T ? first[p + 1] : total;
+    const int64_t E = 19 * kChunk;
+    auto chunk_lo = [&](int64_t node) { return node / kChunk * E; };
+    auto chunk_hi = [&](int64_t node) { return (node / kChunk + 1) * E; };
+    GatherSpan g{0, 0};
+    for (int p = 0; p < T; ++p) {
+        if (last[p] <= first[p]) continue;
+        const int t = tile_at(p, T);
+        int64_t lo = INT64_MAX, hi = 0;
+        for (int d = -1; d <= 1; ++d) {
+            const int q = tile_pos(((t + d) % T + T) % T, T);
+            if (last[q] <= first[q]) continue;
+            lo = std::min(lo, chunk_lo(first[q]));
+            hi = std::max(hi, chunk_hi(last[q] - 1));
+        }
+        g.slack = std::max(g.slack, chunk_lo(last[p] - 1) - lo);
+        g.reach = std::max(g.reach, hi - chunk_lo(first[p]));
+    }
+    return g;
 }
 
 int64_t count_fluid(const uint8_t* g, int nx, int ny, int nz) {
@@ -246,17 +277,6 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                             (uint32_t)x | ((uint32_t)y << bx) | ((uint32_t)z << (bx + by));
             }
     });
-}
-
-void table_to_pull_offsets(int32_t* t, int64_t nf, int64_t stride) {
-    for (int i = 1; i < 19; ++i) {
-        const bool first = (i & 1) != 0;
-        int32_t* row = t + (int64_t)(i - 1) * stride;
-        for (int64_t n = 0; n < nf; ++n) {
-            const int32_t s = row[n];
-            row[n] = s >= 0 ? (int32_t)(s + (first ? 0 : stride)) : (int32_t)(n + (first ? stride : 0));
-        }
-    }
 }
 
 void fluid_voxels(const uint8_t* g, int nx, int ny, int nz, int64_t* out) {

@@ -39,25 +39,42 @@ CoordBits coord_bits(int nx, int ny, int nz);
 // tile -- and the fluid voxels of each row in increasing x.  Rows that are
 // neighbours in y or z then sit at most kNodeTileZ rows apart in the list
 // (except across tile faces), so the cache lines a step gathers from are
-// reused while still in L2.
+// reused while still in L2.  The tiles themselves are folded: tile t of T
+// comes at position 2t when 2t < T, else at 2(T - 1 - t) + 1 (order 0, T-1,
+// 1, T-2, ...), so tiles that touch in z, across the periodic wrap too, are
+// at most two positions apart and every gather stays near its node.
 constexpr int kNodeTileZ = 16;
+inline int tile_at(int p, int T) { return (p & 1) ? T - 1 - (p >> 1) : (p >> 1); }
+inline int tile_pos(int t, int T) { return 2 * t < T ? 2 * t : 2 * (T - 1 - t) + 1; }
 
 // Node number of the first fluid voxel of every row r = z * ny + y
 // (entry ny * nz holds the fluid count).
 std::vector<int64_t> row_starts(const uint8_t* geom, int nx, int ny, int nz);
 
-// Padded node count: the fluid list rounded up to a multiple of 256.
-inline int64_t padded(int64_t nf) { return (nf + 255) / 256 * 256; }
+// Padded node count: the fluid list rounded up to a multiple of kChunk.
+constexpr int kChunk = 256;
+inline int64_t padded(int64_t nf) { return (nf + kChunk - 1) / kChunk * kChunk; }
+
+// Population layout in device memory: the kChunk nodes of chunk q = n / kChunk
+// keep their 19 populations back to back, element (i, n) at
+// q * 19 * kChunk + i * kChunk + n % kChunk.
+inline int64_t state_elem(int i, int64_t n) {
+    return (n / kChunk) * (19 * kChunk) + (int64_t)i * kChunk + n % kChunk;
+}
+
+// The step kernels address a chunk's gathers as 32-bit byte offsets from a
+// base `slack` elements below the chunk.  From the tile structure of the node
+// order (row_starts), gather_span bounds how far below its chunk (slack) and
+// how far past its start (reach) a chunk's gathered elements can lie; the
+// offsets fit when (slack + reach) * element size < 2^32.
+struct GatherSpan {
+    int64_t slack, reach;  // elements
+};
+GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz);
 
 // Pull-source table [18][stride], entry (i-1)*stride + n; -1 = solid source.
 void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_t stride,
                  int32_t* table);
-
-// Rewrites a pull-source table in place into the device form: the element
-// offset of the gathered population relative to the base of its opposite
-// pair (src + (i odd ? i : i-1) * stride), i.e. s (+ stride for even i) for a
-// fluid source, n (+ stride for odd i) at a wall.
-void table_to_pull_offsets(int32_t* table, int64_t nf, int64_t stride);
 
 // Bitmap index.  Every (y, z) row of the image is a padded bit string of
 // nx + 2 positions: position x + 1 holds voxel x, position 0 repeats voxel

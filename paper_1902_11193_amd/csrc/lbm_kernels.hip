@@ -8,8 +8,10 @@
 // (Sec. 2.2), volume-averaged velocity for Darcy's law (Eq. perm_calc).
 //
 // Design for CDNA4: every fluid node is one lane of a wave64; populations are
-// structure-of-arrays [19][stride] so the 19 stores and the in-row gathers are
-// coalesced; the 19x19 transform M and its inverse M^T diag(1/|row|^2) are
+// stored chunk by chunk, the 256 nodes of a chunk (one block's share of a
+// sweep) keeping their 19 populations back to back, so a chunk's 19 stores
+// are one contiguous run and its gathers fall in a few nearby runs rather
+// than 19 separate arrays; the 19x19 transform M and its inverse M^T diag(1/|row|^2) are
 // written out as integer-coefficient adds on pair sums/differences of
 // opposite populations (no MFMA: at ~0.4 kflop per node-update against
 // ~150 bytes of traffic this is an HBM-bound stencil, not a contraction).
@@ -91,57 +93,81 @@ __device__ __forceinline__ void st_stream(T* base, uint32_t byte_off, T v) {
     __builtin_nontemporal_store(v, reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off));
 }
 
-// Element offset of the population gathered in direction i, relative to the
-// base of its opposite pair, src + (i odd ? i : i - 1) * stride: the value
-// pulled from node s, or at a wall the node's own opposite population.
-__device__ __forceinline__ uint32_t pull_offset(int i, int32_t s, uint32_t n, uint32_t stride) {
-    const bool first = (i & 1) != 0;
-    return s >= 0 ? (uint32_t)s + (first ? 0u : stride) : n + (first ? stride : 0u);
+// ------------------------------------------------------------------ layout
+// Element (i, m) of a population array sits at node_elem(m) + i * kThreads:
+// chunk q = m / 256 owns elements [q * 19 * 256, (q + 1) * 19 * 256).
+constexpr uint32_t kChunkElems = 19u * kThreads;
+__device__ __forceinline__ uint32_t node_elem(uint32_t m) {
+    return m + (m >> 8) * (kChunkElems - kThreads);  // = (m / 256) * 19 * 256 + m % 256
 }
-__host__ __device__ constexpr int pair_first(int i) { return (i & 1) ? i : i - 1; }
+
+// Gathers of one chunk go through a wave-uniform base pointer placed `slack`
+// elements below the chunk's first element, with one 32-bit byte offset per
+// lane; the host checks (gather_span) that every element a chunk gathers lies
+// within 2^32 bytes above that base.  Offsets are formed modulo 2^32, which
+// is exact for values that fit.
+template <class T>
+__device__ __forceinline__ const T* chunk_base(const T* p, uint32_t chunk, uint32_t slack) {
+    return p + ((int64_t)chunk * kChunkElems - (int64_t)slack);
+}
+// Byte offset, from the base of chunk cbe / kChunkElems, of the population
+// pulled in direction i: population i of the source node m, or, when the
+// source voxel is solid (m < 0), population opp(i) of the node itself (en =
+// node_elem of the node; halfway bounce-back).
+template <class T, int I>
+__device__ __forceinline__ uint32_t pull_offset(int32_t m, uint32_t en, uint32_t kb) {
+    // both candidates, then a bitwise select: no branch per direction
+    const uint32_t pulled = node_elem((uint32_t)m) + (uint32_t)I * kThreads;
+    const uint32_t own = en + (uint32_t)opp(I) * kThreads;
+    const uint32_t wall = (uint32_t)(m >> 31);  // all ones when m < 0
+    return ((pulled & ~wall) | (own & wall)) * (uint32_t)sizeof(T) + kb;
+}
+// kb of a chunk: (slack - first element of the chunk) * sizeof(T), mod 2^32
+template <class T>
+__device__ __forceinline__ uint32_t chunk_kb(uint32_t chunk, uint32_t slack) {
+    return (slack - chunk * kChunkElems) * (uint32_t)sizeof(T);
+}
+// Offsets of the 19 populations gathered into node n of chunk `chunk`
+// (off[0]: its own rest population) from the pull sources s.
+template <class T>
+__device__ __forceinline__ void gather_offsets(const int32_t s[19], uint32_t n, uint32_t chunk,
+                                               uint32_t slack, uint32_t off[19]) {
+    const uint32_t en = node_elem(n), kb = chunk_kb<T>(chunk, slack);
+    off[0] = en * (uint32_t)sizeof(T) + kb;
+    unroll<18>([&](auto k) {
+        constexpr int i = decltype(k)::value + 1;
+        off[i] = pull_offset<T, i>(s[i], en, kb);
+    });
+}
 
 // ------------------------------------------------------------------ indices
-// An index yields, for node n, the element offsets off[i] (i = 1..18) of the
-// populations pulled into n, each relative to the base of its opposite pair,
-// src + (i odd ? i : i - 1) * stride: the value leaving the node at x_n - c_i,
-// or, when that voxel is solid, the node's own opposite population (halfway
-// bounce-back).  For the adjoint it also yields boff[i], the transposed
-// offsets: the population of direction i that the node at x_n + c_i pulled
-// from n, or at a wall the one n pulled itself.
+// An index yields, for node n, the pull sources s[i] (i = 1..18): the node
+// at x_n - c_i, or -1 when that voxel is solid (halfway bounce-back there).
+// The adjoint reads them transposed, s[opp(i)] being the node at x_n + c_i.
 //
 // Both indices split into load (issue the memory reads for a node) and
 // resolve (arithmetic on what was read), so a caller can overlap the reads of
 // one node with the population traffic of another.
 
-// Device table of pull offsets [18][stride] (built on the host from the
-// pull-source table, see table_to_pull_offsets).
+// Device table of pull sources [18][stride] (entry -1: solid source).
 struct TableIdx {
     const int32_t* __restrict__ t;
     uint32_t stride;
     using Pre = uint32_t;  // nothing to fetch ahead
     __device__ __forceinline__ Pre prefetch(uint32_t) const { return 0u; }
     struct Raw {
-        uint32_t t[19];
+        int32_t t[19];
     };
     __device__ __forceinline__ void load(uint32_t n, Pre, Raw& r) const {
         unroll<18>([&](auto k) {
             constexpr int i = decltype(k)::value + 1;
-            r.t[i] = (uint32_t)ld_off(t + (size_t)(i - 1) * stride, n * 4u);
+            r.t[i] = ld_off(t + (size_t)(i - 1) * stride, n * 4u);
         });
     }
-    __device__ __forceinline__ void resolve(const Raw& r, Pre, uint32_t, uint32_t off[19]) const {
+    __device__ __forceinline__ void sources(const Raw& r, Pre, int32_t s[19]) const {
         unroll<18>([&](auto k) {
             constexpr int i = decltype(k)::value + 1;
-            off[i] = r.t[i];
-        });
-    }
-    // an entry is >= stride exactly when it points into the second array of
-    // the pair, so the transposed offset is the opposite entry moved across
-    __device__ __forceinline__ void transpose(const Raw& r, Pre, uint32_t, uint32_t boff[19]) const {
-        unroll<18>([&](auto k) {
-            constexpr int i = decltype(k)::value + 1;
-            const uint32_t o = r.t[opp(i)];
-            boff[i] = o >= stride ? o - stride : o + stride;
+            s[i] = r.t[i];
         });
     }
 };
@@ -152,7 +178,7 @@ struct TableIdx {
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
     const uint4* __restrict__ rec;
-    uint32_t nx, ny, nz, R, bx, by, stride;
+    uint32_t nx, ny, nz, R, bx, by;
 
     struct RowRaw {
         uint32_t bits, base, count, next;  // record of word x >> 5, low bits of the next
@@ -245,22 +271,6 @@ struct BitmapIdx {
         s[16] = pick(decode(r.pp, x, xf, xl), 0);
         s[17] = pick(decode(r.mp, x, xf, xl), 0);
         s[18] = pick(decode(r.pm, x, xf, xl), 0);
-    }
-    __device__ __forceinline__ void resolve(const Raw& r, Pre c, uint32_t n, uint32_t off[19]) const {
-        int32_t s[19];
-        sources(r, c, s);
-        unroll<18>([&](auto k) {
-            constexpr int i = decltype(k)::value + 1;
-            off[i] = pull_offset(i, s[i], n, stride);
-        });
-    }
-    __device__ __forceinline__ void transpose(const Raw& r, Pre c, uint32_t n, uint32_t boff[19]) const {
-        int32_t s[19];
-        sources(r, c, s);
-        unroll<18>([&](auto k) {
-            constexpr int i = decltype(k)::value + 1;
-            boff[i] = pull_offset(i, s[opp(i)], n, stride);
-        });
     }
 };
 
@@ -433,7 +443,7 @@ k_finalize(const double* __restrict__ partials, int grid, double* __restrict__ o
 template <class C, class Ix, bool FIELD>
 __global__ void __launch_bounds__(kThreads)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
-       uint32_t stride, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
+       uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
        const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
        const double* __restrict__ prev_partials, double* __restrict__ prev_out) {
     using T = typename C::T;
@@ -462,7 +472,9 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
-            ix.resolve(raw, p0, n, off);
+            int32_t s[19];
+            ix.sources(raw, p0, s);
+            gather_offsets<T>(s, n, c, slack, off);
         }
         for (;;) {
             // (1) index loads of the next node, (2) population loads of this
@@ -472,15 +484,19 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             typename Ix::Raw raw;
             ix.load(n1, pre1, raw);
             __builtin_amdgcn_sched_barrier(0);
+            const T* gb = chunk_base(src, c, slack);
             T fr[19];
-            fr[0] = ld_off(src, n * (uint32_t)sizeof(T));
-            unroll<18>([&](auto k) {
-                constexpr int i = decltype(k)::value + 1;
-                fr[i] = ld_off(src + (size_t)pair_first(i) * stride, off[i] * (uint32_t)sizeof(T));
+            unroll<19>([&](auto k) {
+                constexpr int i = decltype(k)::value;
+                fr[i] = ld_off(gb, off[i]);
             });
             const typename Ix::Pre pre2 = ix.prefetch(node_of(c + 2 * G));
             __builtin_amdgcn_sched_barrier(0);
-            ix.resolve(raw, pre1, n1, off);
+            {
+                int32_t s[19];
+                ix.sources(raw, pre1, s);
+                gather_offsets<T>(s, n1, c + G, slack, off);
+            }
             __builtin_amdgcn_sched_barrier(0);
             float f[19];
             unroll<19>([&](auto k) {
@@ -505,9 +521,10 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             acc[1] += live * (double)jy;
             acc[2] += live * (double)jz;
             acc[3] += live * (double)m.rho;
+            T* db = dst + (size_t)c * kChunkElems;
             unroll<19>([&](auto k) {
                 constexpr int i = decltype(k)::value;
-                st_stream(dst + (size_t)i * stride, n * (uint32_t)sizeof(T), C::enc(f[i], scale));
+                st_stream(db + i * kThreads, (n & (kThreads - 1u)) * (uint32_t)sizeof(T), C::enc(f[i], scale));
             });
             c += G;
             if (c >= chunks) break;
@@ -557,7 +574,7 @@ __device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w
 template <class Ix, bool FIELD>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* __restrict__ st,
-          Ix ix, uint32_t stride, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
+          Ix ix, uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
           const float* __restrict__ field, double* __restrict__ dkdF, double* __restrict__ partials) {
     const uint32_t lb = logical_block();
     const uint32_t chunks = (nf + kThreads - 1) / kThreads;
@@ -565,22 +582,26 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
     for (uint32_t c = lb; c < chunks; c += gridDim.x) {
         const uint32_t n = c * kThreads + threadIdx.x;
         if (n >= nf) continue;
-        uint32_t off[19], boff[19];
+        int32_t s[19];
         {
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
-            ix.resolve(raw, p0, n, off);
-            ix.transpose(raw, p0, n, boff);
+            ix.sources(raw, p0, s);
         }
+        // f: the forward's pulls; b: the transposed pulls, direction i from
+        // the node at x_n + c_i (source s[opp(i)]) or at a wall from n itself
+        const uint32_t en = node_elem(n), kb = chunk_kb<float>(c, slack);
+        const float* sb = chunk_base(st, c, slack);
+        const float* ab = chunk_base(ain, c, slack);
         __builtin_amdgcn_sched_barrier(0);
         float f[19], b[19];
-        f[0] = ld_off(st, n * 4u);
-        b[0] = ld_off(ain, n * 4u);
+        f[0] = ld_off(sb, en * 4u + kb);
+        b[0] = ld_off(ab, en * 4u + kb);
         unroll<18>([&](auto k) {
             constexpr int i = decltype(k)::value + 1;
-            f[i] = ld_off(st + (size_t)pair_first(i) * stride, off[i] * 4u);
-            b[i] = ld_off(ain + (size_t)pair_first(i) * stride, boff[i] * 4u);
+            f[i] = ld_off(sb, pull_offset<float, i>(s[i], en, kb));
+            b[i] = ld_off(ab, pull_offset<float, i>(s[opp(i)], en, kb));
         });
         float Fx = Fx0, Fy = Fy0, Fz = Fz0;
         if (FIELD) {
@@ -673,9 +694,10 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
         dkdF[nf + n] += (double)gFy;
         dkdF[2 * (size_t)nf + n] += (double)gFz;
         add_back(b, nu);
+        float* ob = aout + (size_t)c * kChunkElems;
         unroll<19>([&](auto k) {
             constexpr int i = decltype(k)::value;
-            st_off(aout + (size_t)i * stride, n * 4u, b[i]);
+            st_off(ob + i * kThreads, (n & (kThreads - 1u)) * 4u, b[i]);
         });
     }
     double part[6];
@@ -683,10 +705,11 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
     if ((int)threadIdx.x < 6) partials[(size_t)lb * 6 + threadIdx.x] += part[threadIdx.x];
 }
 
-__global__ void k_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa) {
+__global__ void k_seed(float* adj, int64_t nf, int axis, float kappa) {
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nf;
          n += (int64_t)gridDim.x * blockDim.x) {
-        for (int i = 0; i < 19; ++i) adj[(int64_t)i * stride + n] = kappa * (float)cdir(i, axis);
+        const int64_t e = (n / kThreads) * kChunkElems + (n % kThreads);
+        for (int i = 0; i < 19; ++i) adj[e + (int64_t)i * kThreads] = kappa * (float)cdir(i, axis);
     }
 }
 
@@ -709,8 +732,7 @@ int grid_for(int64_t n) {
 TableIdx table_view(const IndexView& v) { return TableIdx{v.table, (uint32_t)v.stride}; }
 BitmapIdx bitmap_view(const IndexView& v) {
     return BitmapIdx{v.coords, static_cast<const uint4*>(v.rec), (uint32_t)v.nx, (uint32_t)v.ny,
-                     (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by,
-                     (uint32_t)v.stride};
+                     (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by};
 }
 
 template <class C, class Ix>
@@ -720,11 +742,11 @@ hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
     T* dst = static_cast<T*>(a.dst);
     if (a.field)
         hipLaunchKernelGGL((k_step<C, Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
-                           (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
+                           (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
                            a.inv_scale, a.partials, a.prev_partials, a.prev_out);
     else
         hipLaunchKernelGGL((k_step<C, Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
-                           ix, (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
+                           ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
                            a.scale, a.inv_scale, a.partials, a.prev_partials, a.prev_out);
     return hipGetLastError();
 }
@@ -739,11 +761,11 @@ template <class Ix>
 hipError_t adjoint_with(const AdjLaunch& a, Ix ix, hipStream_t s) {
     if (a.field)
         hipLaunchKernelGGL((k_adjoint<Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
-                           a.adj_out, a.state, ix, (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates,
+                           a.adj_out, a.state, ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates,
                            a.F[0], a.F[1], a.F[2], a.field, a.dk_dF, a.partials);
     else
         hipLaunchKernelGGL((k_adjoint<Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
-                           a.adj_out, a.state, ix, (uint32_t)a.idx.stride, (uint32_t)a.nf, a.rates,
+                           a.adj_out, a.state, ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates,
                            a.F[0], a.F[1], a.F[2], nullptr, a.dk_dF, a.partials);
     return hipGetLastError();
 }
@@ -816,9 +838,9 @@ hipError_t launch_adjoint_step(const AdjLaunch& a, hipStream_t s) {
     return adjoint_with(a, bitmap_view(a.idx), s);
 }
 
-hipError_t launch_adjoint_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa,
+hipError_t launch_adjoint_seed(float* adj, int64_t nf, int axis, float kappa,
                                hipStream_t s) {
-    hipLaunchKernelGGL(k_seed, dim3(grid_for(nf)), dim3(kThreads), 0, s, adj, stride, nf, axis,
+    hipLaunchKernelGGL(k_seed, dim3(grid_for(nf)), dim3(kThreads), 0, s, adj, nf, axis,
                        kappa);
     return hipGetLastError();
 }

@@ -18,8 +18,9 @@ struct RatesF {
 // Device view of the neighbour index.
 struct IndexView {
     int kind;
-    int64_t stride;             // padded node count (row stride of [19][np] arrays)
-    const int32_t* table;       // kTable: [18][stride]
+    int64_t stride;             // padded node count np (row stride of the table)
+    int64_t slack;              // elements between a chunk's gather base and the chunk (gather_span)
+    const int32_t* table;       // kTable: [18][stride] pull sources, -1 = solid
     const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
     const void* rec;            // kBitmap: [ny*nz*R] 16-byte row-word records
     int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = records per row
@@ -27,8 +28,8 @@ struct IndexView {
 
 struct StepLaunch {
     int storage;
-    const void* src;      // [19][stride] deviations (storage type)
-    void* dst;            // [19][stride]
+    const void* src;      // deviations (storage type), chunked: element (i, n) at state_elem(i, n)
+    void* dst;            // same layout
     IndexView idx;
     int64_t nf;
     RatesF rates;
@@ -59,9 +60,9 @@ hipError_t launch_rescale(int storage, void* p, int64_t count, float factor, hip
 
 // ---------------------------------------------------------------- adjoint
 struct AdjLaunch {
-    const float* adj_in;   // a^{n+1}: [19][stride] adjoint of the gathered populations of step n+1
+    const float* adj_in;   // a^{n+1}: adjoint of the gathered populations of step n+1 (state layout)
     float* adj_out;        // a^n
-    const float* state;    // fh^{n-1}: [19][stride] FP32 deviations
+    const float* state;    // fh^{n-1}: FP32 deviations (state layout)
     IndexView idx;
     int64_t nf;
     RatesF rates;
@@ -73,8 +74,8 @@ struct AdjLaunch {
 };
 hipError_t launch_adjoint_step(const AdjLaunch& a, hipStream_t s);
 
-// a^N seed: adj[i][n] = kappa * c_i[axis] for fluid nodes.
-hipError_t launch_adjoint_seed(float* adj, int64_t stride, int64_t nf, int axis, float kappa,
+// a^N seed: element (i, n) = kappa * c_i[axis] for fluid nodes (state layout).
+hipError_t launch_adjoint_seed(float* adj, int64_t nf, int axis, float kappa,
                                hipStream_t s);
 
 // out[k] = sum over blocks of partials[b][k], k < 6, fixed order.

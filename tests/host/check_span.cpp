@@ -1,0 +1,56 @@
+// Brute-force check of the chunked population layout and its gather span on
+// random periodic images: every element a node's step touches (pull sources,
+// bounce-back own populations, own stores) must lie inside the population
+// array and within [chunk_base - slack, chunk_base + reach) of its chunk, and
+// the node order must be a permutation of the fluid voxels.  Exit status 0
+// when every case holds.
+#include "lbm_host.hpp"
+#include <cstdio>
+#include <random>
+#include <vector>
+using namespace lbm;
+int main() {
+    std::mt19937 rng(5);
+    int bad = 0, cases = 0;
+    for (int it = 0; it < 300; ++it) {
+        int nx = 1 + rng() % 40, ny = 1 + rng() % 40, nz = 1 + rng() % 90;
+        double phi = (rng() % 100) / 100.0;
+        std::vector<uint8_t> g((size_t)nx * ny * nz);
+        std::uniform_real_distribution<double> U(0, 1);
+        for (auto& v : g) v = U(rng) < phi ? 0 : 1;
+        int64_t nf = count_fluid(g.data(), nx, ny, nz);
+        if (nf == 0) continue;
+        ++cases;
+        int64_t np = padded(nf);
+        std::vector<int32_t> t((size_t)18 * np, -1);
+        build_table(g.data(), nx, ny, nz, nf, np, t.data());
+        auto st = row_starts(g.data(), nx, ny, nz);
+        GatherSpan sp = gather_span(st, ny, nz);
+        const int64_t E = 19 * kChunk;
+        for (int64_t n = 0; n < nf; ++n) {
+            int64_t cb = (n / kChunk) * E;
+            auto check = [&](int64_t e) {
+                int64_t rel = e - cb + sp.slack;
+                if (rel < 0 || rel >= sp.slack + sp.reach || e < 0 || e >= 19 * np) {
+                    if (bad < 10) printf("BAD n=%lld e=%lld cb=%lld slack=%lld reach=%lld dims %d %d %d\n",
+                                         (long long)n, (long long)e, (long long)cb, (long long)sp.slack,
+                                         (long long)sp.reach, nx, ny, nz);
+                    ++bad;
+                }
+            };
+            check(state_elem(0, n));
+            for (int i = 1; i < 19; ++i) {
+                int32_t s = t[(size_t)(i - 1) * np + n];
+                check(s >= 0 ? state_elem(i, s) : state_elem(opposite(i), n));
+                check(state_elem(i, n));
+            }
+        }
+        // node order is a permutation of the fluid voxels
+        std::vector<int64_t> vox(nf);
+        fluid_voxels(g.data(), nx, ny, nz, vox.data());
+        std::vector<char> seen((size_t)nx * ny * nz, 0);
+        for (auto v : vox) { if (g[v] != 0 || seen[v]) { ++bad; } seen[v] = 1; }
+    }
+    printf("cases %d bad %d\n", cases, bad);
+    return bad != 0;
+}

@@ -68,11 +68,16 @@ def test_rates_reject():
 
 
 def _brute_node_order(mask, tile=16):
-    """Fluid voxels sorted by (z // tile, y, z % tile, x)."""
+    """Fluid voxels sorted by (position of the z-tile, y, z % tile, x), where the
+    tiles t = z // tile of T are folded into the order 0, T-1, 1, T-2, ..."""
     nz, ny, nx = mask.shape
+    T = -(-nz // tile)
+    t = np.arange(T)
+    pos = np.where(2 * t < T, 2 * t, 2 * (T - 1 - t) + 1)
+    assert np.array_equal(np.sort(pos), t)
     fl = np.flatnonzero(mask.reshape(-1) == 0)
     z, y, x = np.unravel_index(fl, mask.shape)
-    key = np.lexsort((x, z % tile, y, z // tile))
+    key = np.lexsort((x, z % tile, y, pos[z // tile]))
     return fl[key]
 
 
@@ -111,7 +116,7 @@ def test_neighbor_table_brute_force_and_permutation(shape, sf, seed):
     assert (reads == 1).all()
 
 
-@pytest.mark.parametrize("shape", [(5, 6, 7), (40, 3, 9), (33, 17, 2)])
+@pytest.mark.parametrize("shape", [(5, 6, 7), (40, 3, 9), (33, 17, 2), (64, 2, 3), (70, 3, 4)])
 def test_node_order_is_z_tiled_rows(shape):
     mask = random_mask(shape, 0.3, 4)
     order = P.lbm_node_order(mask)
@@ -167,3 +172,22 @@ def test_setup_validates_before_any_device_call():
     assert _setup_rc(m, ws=fake, nbytes=16) == P.LBM_EWORKSPACE
     assert _setup_rc(m, ws=ctypes.c_void_p(4096 + 8), nbytes=1 << 40) == P.LBM_EWORKSPACE
     assert b"workspace" in P.lib().lbm_last_error()
+
+
+def test_gather_span_bounds_brute_force(tmp_path):
+    """The step kernels address a chunk's gathers from one base pointer with
+    32-bit offsets; the host bound on how far they reach (gather_span) must
+    cover every access, checked element by element on random images."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_1902_11193_amd", "csrc")
+    exe = tmp_path / "check_span"
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", csrc, os.path.join(root, "tests", "host", "check_span.cpp"),
+                    os.path.join(csrc, "lbm_host.cpp"), "-o", str(exe), "-lpthread"], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "bad 0" in r.stdout
