@@ -115,10 +115,12 @@ def run_steady(P, mask, args, storage):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done, conv, k = 0, False, float("nan")
+    trajectory = []
     while done < args.max_steps and not conv:
         r = s.run_to_steady(eps=args.eps, check_every=100, max_steps=min(2000, args.max_steps - done))
         done += r["steps"]
         conv, k = r["converged"], float(r["k"][0])
+        trajectory.append((done, k))
         print(f"[bench] steady {storage}: {done} steps, k = {k:.9g}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -132,7 +134,7 @@ def run_steady(P, mask, args, storage):
     del s
     torch.cuda.empty_cache()
     return dict(storage=storage, steps=done, converged=conv, k=k, seconds=t, MFLUPS=nf * done / t / 1e6,
-                eps=args.eps, extra_steps=args.steady_extra, k_after_extra=k_extra,
+                eps=args.eps, trajectory=trajectory, extra_steps=args.steady_extra, k_after_extra=k_extra,
                 k_drift_after_extra=k_extra / k - 1)
 
 
