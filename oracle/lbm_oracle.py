@@ -28,6 +28,8 @@ Models for Micro-tomographic Pore-spaces", arXiv:1902.11193):
   shifted velocity u = (sum_i f_i c_i + F/2)/rho0 and projected with M;
 * halfway bounce-back at solid voxels (Sec. 2.2, the wall midway between a
   fluid and a solid voxel) in a periodic box with a body force (Sec. 2.2);
+* the two-relaxation-time collision in velocity space (Sec. 2.1.2), the
+  link-wise form of the MRT collision for two-rate sets (SRT, B, E);
 * the Darcy permeability k_j = nu <u_j> / g_j from the volume-averaged
   velocity (Sec. 3, Eq. perm_calc) and the per-step convergence test
   (Eq. convergence).
@@ -278,6 +280,59 @@ def collide(f: torch.Tensor, s: torch.Tensor, F: torch.Tensor, lat: Lattice,
     return lat.Minv @ mstar
 
 
+# --------------------------------------------------------------------------
+# Two-relaxation-time collision in velocity space (Sec. 2.1.2)
+# --------------------------------------------------------------------------
+EVEN_ROWS = [1, 2, 9, 10, 11, 12, 13, 14, 15]   # e, eps, 3pxx, 3pixx, pww, piww, pxy, pyz, pxz
+ODD_ROWS = [4, 6, 8, 16, 17, 18]                 # qx, qy, qz, mx, my, mz
+
+
+def trt_rates(s: torch.Tensor):
+    """(s+, s-) of a rate vector that is a two-relaxation-time set: every
+    non-conserved even moment relaxes at s+ and every odd one at s- (SRT, Set B
+    and Set E of Table 2 are; Sets A, C and D are not)."""
+    even, odd = s[EVEN_ROWS], s[ODD_ROWS]
+    if not (bool((even == even[0]).all()) and bool((odd == odd[0]).all())):
+        raise ValueError("the rates are not a two-relaxation-time set")
+    return even[0], odd[0]
+
+
+def equilibrium(c: torch.Tensor, w: torch.Tensor, rho: torch.Tensor, j: torch.Tensor,
+                linear: bool = False) -> torch.Tensor:
+    """Incompressible second-order equilibrium in velocity space, rho0 = 1:
+    f_eq,i = w_i [rho + 3 c_i.j + 9/2 (c_i.j)^2 - 3/2 j.j]; ``linear`` drops the
+    quadratic terms.  Its moments are the m_eq of Eq. MRT Equi as read here."""
+    cj = c.to(DT) @ j
+    out = rho[None, :] + 3.0 * cj
+    if not linear:
+        out = out + (4.5 * cj * cj - 1.5 * (j * j).sum(0)[None, :]) / RHO0
+    return w[:, None] * out
+
+
+def collide_trt(f: torch.Tensor, s: torch.Tensor, F: torch.Tensor, lat: Lattice,
+                linear: bool = False) -> torch.Tensor:
+    """Link-wise TRT collision with Guo forcing; ``f``: (19, N), ``F``: (3, N).
+
+    Each population and its opposite split into a symmetric part
+    (f_i + f_ibar)/2 and an antisymmetric part (f_i - f_ibar)/2.  The symmetric
+    parts relax towards those of f_eq at s+ and gain (1 - s+/2) times those of
+    Guo's F_i; the antisymmetric parts do the same with s-.  With j the shifted
+    momentum in f_eq this is the MRT collision of a two-rate set: the
+    momentum, which MRT leaves unrelaxed, gains s- F/2 from the relaxation
+    towards f_eq(j) and (1 - s-/2) F from the source, F in all.
+    """
+    sp, sm = trt_rates(s)
+    opp = lat.opp
+    rho = f.sum(0)
+    j = lat.c.to(DT).T @ f + 0.5 * F
+    feq = equilibrium(lat.c, lat.w, rho, j, linear)
+    Fi = guo_source(lat.c, lat.w, j / RHO0, F, linear)
+    sym = lambda a: 0.5 * (a + a[opp])
+    anti = lambda a: 0.5 * (a - a[opp])
+    return (f - sp * (sym(f) - sym(feq)) - sm * (anti(f) - anti(feq))
+            + (1.0 - 0.5 * sp) * sym(Fi) + (1.0 - 0.5 * sm) * anti(Fi))
+
+
 def rest_state(fluid: torch.Tensor, lat: Lattice) -> torch.Tensor:
     """Initial state f_i = w_i rho0 at fluid voxels, 0 in solid."""
     return lat.w[:, None, None, None] * RHO0 * fluid.to(DT)[None]
@@ -287,8 +342,11 @@ class Problem:
     """A voxel image with its parameters; dense FP64 state on the CPU."""
 
     def __init__(self, mask: np.ndarray, tau: float, Lambda: float | None, rset: str,
-                 g, g_field: np.ndarray | None = None, linear: bool = False):
+                 g, g_field: np.ndarray | None = None, linear: bool = False, collision: str = "mrt"):
         self.lat = Lattice.make()
+        if collision not in ("mrt", "trt"):
+            raise ValueError("collision must be 'mrt' or 'trt'")
+        self.collision = collision
         mask = np.asarray(mask)
         self.shape = mask.shape
         self.solid = torch.from_numpy(mask != 0)
@@ -308,6 +366,8 @@ class Problem:
             gf = torch.from_numpy(np.asarray(g_field, dtype=np.float64))[:, self.fluid]
         self.F = RHO0 * gf.clone()          # force density at fluid voxels, (3, N_f)
         self.s = rates(rset, self.tau, self.Lambda)
+        if collision == "trt":
+            trt_rates(self.s)
         self.nu = viscosity(self.tau)
 
     def initial(self) -> torch.Tensor:
@@ -320,7 +380,8 @@ class Problem:
         f = stream(fh, self.solid, self.lat)
         ff = f[:, self.fluid]
         out = torch.zeros_like(fh)
-        out[:, self.fluid] = collide(ff, s, F, self.lat, self.linear)
+        col = collide_trt if self.collision == "trt" else collide
+        out[:, self.fluid] = col(ff, s, F, self.lat, self.linear)
         _, _, _, u = macroscopic(ff, F, self.lat)
         return out, u
 
@@ -456,5 +517,6 @@ __all__ = [
     "velocities", "weights", "opposite", "moment_matrix", "equilibrium_moments", "guo_source",
     "rates", "viscosity", "Lattice", "stream", "macroscopic", "collide", "rest_state",
     "Problem", "run", "run_to_steady", "state_at_fluid", "gradients", "unit_darcy",
-    "time_steps", "SETS", "MOMENT_NAMES", "RHO0",
+    "time_steps", "SETS", "MOMENT_NAMES", "RHO0", "trt_rates", "equilibrium", "collide_trt",
+    "EVEN_ROWS", "ODD_ROWS",
 ]

@@ -362,3 +362,52 @@ def test_tau_independence_sets_b_d_e_not_a_c_srt():
     for rs in ("A", "C", "SRT"):
         k = [_k_linear(m, rs, t, None) for t in taus]
         assert abs(k[1] / k[0] - 1) > 1e-3, rs
+
+
+# ---------------------------------------------------------------- TRT (Sec. 2.1.2)
+def test_velocity_space_equilibrium_has_the_equilibrium_moments():
+    g = torch.Generator().manual_seed(11)
+    rho = 0.01 * torch.randn(30, generator=g, dtype=torch.float64)
+    j = 0.05 * torch.randn(3, 30, generator=g, dtype=torch.float64)
+    for linear in (False, True):
+        feq = O.equilibrium(LAT.c, LAT.w, rho, j, linear)
+        assert torch.allclose(LAT.M @ feq, O.equilibrium_moments(rho, j, linear), atol=1e-15)
+
+
+@pytest.mark.parametrize("rset,tau,Lam", [("SRT", 0.7, None), ("SRT", 1.4, None), ("B", 0.8, None),
+                                           ("B", 1.6, None), ("E", 1.0, 3 / 16), ("E", 0.6, 1 / 64),
+                                           ("E", 1.3, 3 / 8)])
+@pytest.mark.parametrize("linear", [False, True])
+def test_trt_collision_equals_mrt_for_two_rate_sets(rset, tau, Lam, linear):
+    """The link-wise two-rate collision in velocity space and the moment-space
+    MRT collision are one map for SRT, B and E: checked on random states and
+    forces, including the momentum gain F."""
+    g = torch.Generator().manual_seed(12)
+    f = LAT.w[:, None] * (1 + 0.02 * torch.randn(19, 64, generator=g, dtype=torch.float64))
+    F = 1e-3 * torch.randn(3, 64, generator=g, dtype=torch.float64)
+    s = O.rates(rset, tau, Lam)
+    a = O.collide(f, s, F, LAT, linear)
+    b = O.collide_trt(f, s, F, LAT, linear)
+    assert float((a - b).abs().max()) < 1e-15
+    assert torch.allclose(C.T @ b, C.T @ f + F, atol=1e-16)
+
+
+@pytest.mark.parametrize("rset", ["A", "C", "D"])
+def test_trt_rejects_sets_that_are_not_two_rate(rset):
+    with pytest.raises(ValueError):
+        O.trt_rates(O.rates(rset, 0.9, None))
+    with pytest.raises(ValueError):
+        O.Problem(np.zeros((3, 3, 3), np.uint8), 0.9, None, rset, (1e-6, 0, 0), collision="trt")
+
+
+def test_trt_slit_exact_profile():
+    """TRT alone reproduces the slit's exact steady profile at Lambda_eff (Set E)."""
+    H, Ly, tau, Lam, g = 8, 10, 0.8, 1 / 12, 1e-6
+    p = O.Problem(slit(1, Ly, 1, H), tau, Lam, "E", (g, 0, 0), linear=True, collision="trt")
+    r = O.run_to_steady(p, 1e-14, 100000)
+    assert r["converged"]
+    nu = (tau - 0.5) / 3
+    _, u = p.step(r["state"])
+    y = np.arange(H) - (H - 1) / 2
+    want = (g / (2 * nu)) * ((H / 2) ** 2 - y ** 2) + (g / nu) * (16 * Lam - 3) / 24
+    assert np.abs(u[0].numpy() / want - 1).max() < 1e-8
