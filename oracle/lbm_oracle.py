@@ -28,6 +28,8 @@ Models for Micro-tomographic Pore-spaces", arXiv:1902.11193):
   shifted velocity u = (sum_i f_i c_i + F/2)/rho0 and projected with M;
 * halfway bounce-back at solid voxels (Sec. 2.2, the wall midway between a
   fluid and a solid voxel) in a periodic box with a body force (Sec. 2.2);
+  as options, the paper's full-way bounce-back and symmetry (mirror) planes
+  on the box faces (Sec. 2.2);
 * the two-relaxation-time collision in velocity space (Sec. 2.1.2), the
   link-wise form of the MRT collision for two-rate sets (SRT, B, E);
 * the Darcy permeability k_j = nu <u_j> / g_j from the volume-averaged
@@ -258,6 +260,55 @@ def stream(fh: torch.Tensor, solid: torch.Tensor, lat: Lattice) -> torch.Tensor:
     return out
 
 
+def mirror(i: int, axis: int, lat: Lattice) -> int:
+    """Index of the velocity c_i reflected in ``axis`` (0 = x, 1 = y, 2 = z)."""
+    c = lat.c[i].clone()
+    c[axis] = -c[axis]
+    return int(torch.nonzero((lat.c == c).all(1))[0])
+
+
+def stream_general(fh: torch.Tensor, solid: torch.Tensor, lat: Lattice, symmetric=(False, False, False),
+                   fh_wall: torch.Tensor | None = None) -> torch.Tensor:
+    """Pull streaming written out voxel by voxel (index arrays), with two
+    options the periodic ``stream`` lacks:
+
+    * ``symmetric[a]``: the box faces normal to axis a are symmetry (mirror)
+      planes, half a voxel outside the first and last layers (Sec. 2.2): a pull
+      that leaves the box through such a face takes, from the voxel reached by
+      the tangential part of the step alone, the population of the velocity
+      mirrored in that axis;
+    * ``fh_wall``: the state the bounce-back reads, fh itself for halfway
+      bounce-back, or the state one step older for full-way bounce-back, where
+      a population reaches the wall voxel, turns there at the next collision
+      and comes back one step later than with the wall midway (Sec. 2.2).
+
+    Halfway bounce-back applies when the (mirrored) source voxel is solid.
+    """
+    nz, ny, nx = solid.shape
+    n = (nx, ny, nz)
+    wall_state = fh if fh_wall is None else fh_wall
+    z, y, x = torch.meshgrid(torch.arange(nz), torch.arange(ny), torch.arange(nx), indexing="ij")
+    coord = (x, y, z)
+    mtab = [torch.tensor([mirror(p, a, lat) for p in range(19)]) for a in range(3)]
+    out = torch.empty_like(fh)
+    for i in range(19):
+        src = [coord[a] - int(lat.c[i][a]) for a in range(3)]
+        pop = torch.full(solid.shape, i, dtype=torch.long)
+        for a in range(3):
+            if symmetric[a]:
+                # |c_a| <= 1: a pull that leaves the box comes from the voxel
+                # itself in axis a, with the velocity mirrored in that axis
+                leaves = (src[a] < 0) | (src[a] >= n[a])
+                src[a] = torch.where(leaves, coord[a], src[a])
+                pop = torch.where(leaves, mtab[a][pop], pop)
+            src[a] = src[a] % n[a]
+        from_solid = solid[src[2], src[1], src[0]]
+        pulled = fh[pop, src[2], src[1], src[0]]
+        bounced = wall_state[int(lat.opp[i])]
+        out[i] = torch.where(from_solid, bounced, pulled)
+    return out
+
+
 def macroscopic(f: torch.Tensor, F: torch.Tensor, lat: Lattice):
     """rho = sum f, shifted momentum j = sum f c + F/2, u = j / rho0."""
     m = lat.M @ f
@@ -342,8 +393,14 @@ class Problem:
     """A voxel image with its parameters; dense FP64 state on the CPU."""
 
     def __init__(self, mask: np.ndarray, tau: float, Lambda: float | None, rset: str,
-                 g, g_field: np.ndarray | None = None, linear: bool = False, collision: str = "mrt"):
+                 g, g_field: np.ndarray | None = None, linear: bool = False, collision: str = "mrt",
+                 symmetric: str = "", fullway: bool = False):
         self.lat = Lattice.make()
+        # symmetry planes on the faces normal to the named axes (subset of "xyz"),
+        # and full-way instead of halfway bounce-back (Sec. 2.2)
+        self.symmetric = tuple(a in symmetric for a in "xyz")
+        self.fullway = bool(fullway)
+        self.general = any(self.symmetric) or self.fullway
         if collision not in ("mrt", "trt"):
             raise ValueError("collision must be 'mrt' or 'trt'")
         self.collision = collision
@@ -371,13 +428,25 @@ class Problem:
         self.nu = viscosity(self.tau)
 
     def initial(self) -> torch.Tensor:
-        return rest_state(self.fluid, self.lat)
+        """fh at rest; with full-way bounce-back the state also carries the
+        previous step's fh (stacked: [this step, one step older])."""
+        r = rest_state(self.fluid, self.lat)
+        return torch.stack([r, r.clone()]) if self.fullway else r
 
     def step(self, fh: torch.Tensor, s=None, F=None):
         """One step: gather, then collide.  Returns (new fh, u of this step)."""
         s = self.s if s is None else s
         F = self.F if F is None else F
-        f = stream(fh, self.solid, self.lat)
+        if self.fullway:
+            new, u = self._step(fh[0], s, F, fh_wall=fh[1])
+            return torch.stack([new, fh[0]]), u
+        return self._step(fh, s, F)
+
+    def _step(self, fh, s, F, fh_wall=None):
+        if self.general:
+            f = stream_general(fh, self.solid, self.lat, self.symmetric, fh_wall)
+        else:
+            f = stream(fh, self.solid, self.lat)
         ff = f[:, self.fluid]
         out = torch.zeros_like(fh)
         col = collide_trt if self.collision == "trt" else collide
@@ -440,6 +509,8 @@ def gradients(problem: Problem, n_steps: int, segment: int = 50):
     the problem was built with.  The forward is recomputed segment by segment
     (``segment`` steps each) so memory stays bounded.
     """
+    if problem.general:
+        raise NotImplementedError("gradients are for the periodic halfway bounce-back problem")
     axis = int(torch.argmax(problem.g.abs()))
     gref = float(problem.g[axis])
     tau_t = torch.tensor(problem.tau, dtype=DT, requires_grad=True)
@@ -518,5 +589,5 @@ __all__ = [
     "rates", "viscosity", "Lattice", "stream", "macroscopic", "collide", "rest_state",
     "Problem", "run", "run_to_steady", "state_at_fluid", "gradients", "unit_darcy",
     "time_steps", "SETS", "MOMENT_NAMES", "RHO0", "trt_rates", "equilibrium", "collide_trt",
-    "EVEN_ROWS", "ODD_ROWS",
+    "EVEN_ROWS", "ODD_ROWS", "mirror", "stream_general",
 ]

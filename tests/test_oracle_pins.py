@@ -15,7 +15,7 @@ import pytest
 import torch
 
 import oracle as O
-from lbm_inputs import slit, duct, sphere, random_mask
+from lbm_inputs import slit, duct, sphere, random_mask, percolating_x
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
 LAT = O.Lattice.make()
@@ -411,3 +411,80 @@ def test_trt_slit_exact_profile():
     y = np.arange(H) - (H - 1) / 2
     want = (g / (2 * nu)) * ((H / 2) ** 2 - y ** 2) + (g / nu) * (16 * Lam - 3) / 24
     assert np.abs(u[0].numpy() / want - 1).max() < 1e-8
+
+
+# ---------------------------------------------------------------- symmetry planes, full-way bounce-back (Sec. 2.2)
+def _mirror_yz(m):
+    mm = np.concatenate([m, m[:, ::-1, :]], axis=1)
+    return np.concatenate([mm, mm[::-1]], axis=0)
+
+
+def test_symmetry_planes_equal_the_mirrored_periodic_box():
+    """Mirror planes on the y and z faces are the periodic box of the image
+    reflected in y and z, restricted to the original quarter."""
+    m = random_mask((5, 6, 7), 0.3, 3)
+    ps = O.Problem(m, 0.9, 3 / 16, "E", (1e-4, 0, 0), symmetric="yz")
+    pm = O.Problem(_mirror_yz(m), 0.9, 3 / 16, "E", (1e-4, 0, 0))
+    a, b = ps.initial(), pm.initial()
+    nz, ny, _ = m.shape
+    for _ in range(30):
+        a, ua = ps.step(a)
+        b, ub = pm.step(b)
+    assert float((a - b[:, :nz, :ny, :]).abs().max()) < 1e-14
+    # the driven component; transverse means cancel over the mirrored box only
+    assert abs(float(ps.mean_velocity(ua)[0] / pm.mean_velocity(ub)[0]) - 1) < 1e-12
+
+
+def test_symmetry_plane_closes_a_half_slit():
+    """A wall below and a mirror plane above: half of the slit of twice the
+    height, with its exact profile (Set E, linear equilibrium)."""
+    H, tau, Lam, g = 5, 0.8, 1 / 12, 1e-6
+    m = np.zeros((1, H + 1, 1), np.uint8)
+    m[:, 0, :] = 1
+    p = O.Problem(m, tau, Lam, "E", (g, 0, 0), linear=True, symmetric="y")
+    r = O.run_to_steady(p, 1e-14, 100000)
+    assert r["converged"]
+    _, u = p.step(r["state"])
+    nu = (tau - 0.5) / 3
+    y = np.arange(1, H + 1) - (H + 0.5)
+    want = (g / (2 * nu)) * (H * H - y ** 2) + (g / nu) * (16 * Lam - 3) / 24
+    assert np.abs(u[0].numpy() / want - 1).max() < 1e-8
+
+
+def test_symmetry_planes_open_box_accelerates_freely():
+    p = O.Problem(np.zeros((4, 5, 3), np.uint8), 1.0, 3 / 16, "E", (1e-5, 0, 0), symmetric="yz")
+    r = O.run(p, 20)
+    n = np.arange(1, 21)
+    assert np.abs(r["umean"][:, 0].numpy() - (n - 0.5) * 1e-5).max() < 2e-15
+    assert float(r["umean"][:, 1:].abs().max()) < 1e-15
+
+
+def test_fullway_bounce_back_reads_the_older_state_at_walls():
+    """Full-way bounce-back: at a wall link the population comes back from the
+    state one step older; every other link pulls as before."""
+    lat = O.Lattice.make()
+    m = random_mask((4, 5, 6), 0.35, 9)
+    solid = torch.from_numpy(m != 0)
+    g = torch.Generator().manual_seed(4)
+    fh = torch.randn((19,) + m.shape, generator=g, dtype=torch.float64)
+    old = torch.randn((19,) + m.shape, generator=g, dtype=torch.float64)
+    half = O.stream(fh, solid, lat)
+    full = O.stream_general(fh, solid, lat, fh_wall=old)
+    for i in range(19):
+        cx, cy, cz = (int(v) for v in lat.c[i])
+        wall = torch.roll(solid, shifts=(cz, cy, cx), dims=(0, 1, 2))
+        assert torch.equal(full[i][~wall], half[i][~wall])
+        assert torch.equal(full[i][wall], old[int(lat.opp[i])][wall])
+
+
+def test_fullway_steady_state_equals_halfway():
+    """Full-way bounce-back only delays wall reflections by one step, so the
+    steady state at fluid nodes is the halfway one (linear equilibrium)."""
+    m = percolating_x(random_mask((7, 7, 7), 0.25, 5))
+    ks = []
+    for fw in (False, True):
+        p = O.Problem(m, 1.0, 3 / 16, "E", (1e-5, 0, 0), linear=True, fullway=fw)
+        r = O.run_to_steady(p, 1e-13, 200000)
+        assert r["converged"]
+        ks.append(float(r["k"][0]))
+    assert abs(ks[1] / ks[0] - 1) < 1e-9
