@@ -69,10 +69,11 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1) / steps, wall
 
 
-def run_forward(P, mask, args, storage):
+def run_forward(P, mask, args, storage, collision="mrt"):
     import torch
 
     s = P.Solver(mask, args.tau, args.Lambda, "E", (args.g, 0.0, 0.0), storage, args.index)
+    s.set_collision(collision)
     ms, wall = time_steps(s, args.steps, args.warmup)
     k = float(s.permeability()[0])
     nf = s.n_fluid
@@ -159,7 +160,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grf_512")
     ap.add_argument("--index", default="bitmap", choices=["bitmap", "table"])
-    ap.add_argument("--variants", default="f16,bf16,adjoint")
+    ap.add_argument("--variants", default="f16,bf16,trt,f16_trt,adjoint")
     ap.add_argument("--tau", type=float, default=1.0)
     ap.add_argument("--Lambda", type=float, default=3 / 16)
     ap.add_argument("--g", type=float, default=None)
@@ -211,6 +212,12 @@ def main():
         if v in ("f16", "bf16"):
             variants[f"{v}_store"] = run_forward(P, mask, args, v)
             variants[f"{v}_store"]["k_rel_vs_f32"] = variants[f"{v}_store"]["k_after_timed"] / main_r["k_after_timed"] - 1
+        elif v in ("trt", "f16_trt"):
+            st = "f16" if v == "f16_trt" else "f32"
+            variants[f"{v}_collision"] = run_forward(P, mask, args, st, "trt")
+            base = main_r if st == "f32" else variants.get("f16_store")
+            if base:
+                variants[f"{v}_collision"]["k_rel_vs_mrt"] = variants[f"{v}_collision"]["k_after_timed"] / base["k_after_timed"] - 1
         elif v == "adjoint":
             variants["adjoint"] = run_adjoint(P, mask, args)
         print(f"[bench] {v} done", file=sys.stderr, flush=True)

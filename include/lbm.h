@@ -88,6 +88,27 @@ extern "C" {
 #define LBM_INDEX_TABLE 0
 #define LBM_INDEX_BITMAP 1
 
+/* Collision kernels (lbm_set_collision).
+ * LBM_COLLIDE_MRT: the moment-space collision of Sec. 2.1.1 (Eq. MRT-LBE),
+ *                  any relaxation set.  The default.
+ * LBM_COLLIDE_TRT: the same map written link-wise on opposite pairs (the
+ *                  two-relaxation-time form of Sec. 2.1.2), for sets whose
+ *                  even non-conserved moments share one rate and odd ones
+ *                  another: SRT, Set B, Set E.  Equal to MRT up to rounding. */
+#define LBM_COLLIDE_MRT 0
+#define LBM_COLLIDE_TRT 1
+
+/* Wall schemes (lbm_set_wall).
+ * LBM_WALL_HALFWAY: the wall midway between a fluid and a solid voxel; a
+ *                   population sent into it returns at the next step.  The
+ *                   default, and the scheme every other statement here uses.
+ * LBM_WALL_FULLWAY: the paper's full-way bounce-back (Sec. 2.2): the
+ *                   population travels to the solid voxel, turns there at the
+ *                   next collision and returns one step later than halfway.
+ *                   The steady state at fluid nodes is the same. */
+#define LBM_WALL_HALFWAY 0
+#define LBM_WALL_FULLWAY 1
+
 typedef struct lbm_ctx lbm_ctx;
 
 /* Host only.  The velocity order above: c[i][0..2] = (cx, cy, cz). */
@@ -109,6 +130,25 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
  * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16). */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
+
+/* Host only.  Non-periodic image stacks (Sec. 2.2, the paper's sphere-pack
+ * setup): `pad` fluid-only layers are added before and after the image along
+ * x, the driven axis, and with mirror_y / mirror_z the image is reflected
+ * across its y / z faces.  In the periodic box this gives, the reflected faces
+ * are symmetry (mirror) planes (zero normal velocity, zero normal gradients)
+ * and the padding separates outlet from inlet.  lbm_boundary_dims returns
+ * the new extents: nx + 2 pad, ny (2 ny with mirror_y), nz (2 nz with
+ * mirror_z).  lbm_boundary_image writes the new uint8 image
+ * [onz][ony][onx] to `out` (caller-owned, host).  The flow in the original
+ * image is that of the new box for x in [pad, pad + nx), y < ny, z < nz; the
+ * superficial <u_x> is the same over the whole new box, so lbm_permeability
+ * of a context built on it is that of the padded sample with the body force
+ * on every fluid voxel, as in the paper.  LBM_EINVAL: bad extents, pad
+ * outside [0, 2^20], NULL pointers; LBM_ERANGE: new extents too large. */
+int lbm_boundary_dims(int nx, int ny, int nz, int pad, int mirror_y, int mirror_z, int* onx, int* ony,
+                      int* onz);
+int lbm_boundary_image(const uint8_t* geometry, int nx, int ny, int nz, int pad, int mirror_y, int mirror_z,
+                       uint8_t* out);
 
 /* Host only (no GPU needed).  Linear voxel id x + nx (y + ny z) of every
  * node, in node order: voxel[n_fluid] int64, owned by the caller. */
@@ -178,6 +218,23 @@ int lbm_fluid_index(lbm_ctx* ctx, int64_t* voxel);
 int lbm_set_force_field(lbm_ctx* ctx, const float* g_device);
 
 int64_t lbm_n_fluid(const lbm_ctx* ctx);
+
+/* Host + enqueue.  Chooses the collision kernel for the following steps
+ * (LBM_COLLIDE_MRT or LBM_COLLIDE_TRT, see above); flushes a pending
+ * reduction first.  LBM_EINVAL for an unknown kind or for TRT with a set that
+ * is not two-rate (A, C, D); the context is then unchanged. */
+int lbm_set_collision(lbm_ctx* ctx, int collision);
+
+/* Host + enqueue.  Chooses the wall scheme for the following steps.
+ * LBM_WALL_FULLWAY needs FP32 storage and a device workspace of
+ * lbm_wall_workspace_query bytes (256-byte aligned, caller-owned, must outlive
+ * the mode): it holds every node's populations of one step earlier, and is
+ * initialised to the current state (as is again by lbm_set_state).
+ * LBM_WALL_HALFWAY releases it (workspace may be NULL).  Errors: LBM_EINVAL
+ * (unknown mode, FP16/BF16 storage), LBM_EWORKSPACE.  lbm_adjoint refuses a
+ * context in full-way mode. */
+int lbm_wall_workspace_query(lbm_ctx* ctx, size_t* bytes);
+int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes);
 
 /* FP16 storage keeps 2^e (f_i - w_i rho0); e defaults to
  * round(-log2 max|g|) - 4.  May be changed at any time (the state is

@@ -23,6 +23,8 @@ LBM_OK, LBM_EINVAL, LBM_ENOFLUID, LBM_EWORKSPACE, LBM_EHIP, LBM_ENAN, LBM_ERANGE
 SETS = {"SRT": 0, "A": 1, "B": 2, "C": 3, "D": 4, "E": 5}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 INDEX = {"table": 0, "bitmap": 1}
+COLLISION = {"mrt": 0, "trt": 1}
+WALL = {"halfway": 0, "fullway": 1}
 
 # Every symbol of include/lbm.h with its C signature.
 SIGNATURES = {
@@ -47,6 +49,11 @@ SIGNATURES = {
     "lbm_set_force_field": (c_int, [c_void_p, c_void_p]),
     "lbm_n_fluid": (c_int64, [c_void_p]),
     "lbm_set_storage_exponent": (c_int, [c_void_p, c_int]),
+    "lbm_set_collision": (c_int, [c_void_p, c_int]),
+    "lbm_wall_workspace_query": (c_int, [c_void_p, c_void_p]),
+    "lbm_set_wall": (c_int, [c_void_p, c_int, c_void_p, c_size_t]),
+    "lbm_boundary_dims": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "lbm_boundary_image": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p]),
     "lbm_adjoint_workspace_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
     "lbm_adjoint": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, POINTER(c_double), POINTER(c_double),
                             POINTER(c_double), c_void_p]),
@@ -135,6 +142,19 @@ def lbm_node_order(geometry) -> np.ndarray:
     return v[:nf]
 
 
+def lbm_boundary_image(geometry, pad: int = 5, mirror_y: bool = True, mirror_z: bool = True) -> np.ndarray:
+    """The image padded along x with `pad` fluid layers per side and reflected
+    across its y / z faces (symmetry planes in the periodic box)."""
+    g, nx, ny, nz = _geom(geometry)
+    o = (c_int * 3)()
+    _check(lib().lbm_boundary_dims(nx, ny, nz, int(pad), int(bool(mirror_y)), int(bool(mirror_z)),
+                                   ctypes.byref(o, 0), ctypes.byref(o, 4), ctypes.byref(o, 8)))
+    out = np.empty((o[2], o[1], o[0]), np.uint8)
+    _check(lib().lbm_boundary_image(_dptr(g, c_uint8), nx, ny, nz, int(pad), int(bool(mirror_y)),
+                                    int(bool(mirror_z)), _dptr(out, c_uint8)))
+    return out
+
+
 def raster_permutation(geometry) -> np.ndarray:
     """perm with raster_list[perm[k]] = node k: position of every node in the
     raster-ordered (x fastest) list of fluid voxels."""
@@ -171,6 +191,7 @@ class Solver:
                                c_void_p(self.stream.cuda_stream)))
         self._ctx = ctx
         self._field = None
+        self._wall_ws = None
 
     # -- stepping and observables
     def step(self, n: int = 1):
@@ -239,6 +260,22 @@ class Solver:
     def set_storage_exponent(self, e: int):
         _check(lib().lbm_set_storage_exponent(self._ctx, int(e)))
 
+    def set_collision(self, kind: str):
+        """'mrt' (moment space, any set) or 'trt' (link-wise, SRT / B / E)."""
+        _check(lib().lbm_set_collision(self._ctx, COLLISION[kind]))
+
+    def set_wall(self, kind: str):
+        """'halfway' (default) or 'fullway' bounce-back (FP32 storage)."""
+        if kind == "halfway":
+            _check(lib().lbm_set_wall(self._ctx, WALL[kind], None, 0))
+            self._wall_ws = None
+            return
+        nbytes = c_size_t(0)
+        _check(lib().lbm_wall_workspace_query(self._ctx, byref(nbytes)))
+        ws = self._torch.empty(nbytes.value, dtype=self._torch.uint8, device=self.device)
+        _check(lib().lbm_set_wall(self._ctx, WALL[kind], c_void_p(ws.data_ptr()), nbytes.value))
+        self._wall_ws = ws
+
     # -- adjoint
     def adjoint(self, n_steps: int, checkpoint_every: int = 200):
         """k_N and dk/dtau, dk/dLambda, dk/dg (CUDA float64 (3, n_fluid))."""
@@ -306,4 +343,4 @@ def permeability(geometry, tau, Lambda, g_field, relaxation_set="E", g_ref=(1e-6
 
 
 __all__ = ["lib", "LbmError", "Solver", "permeability", "lbm_velocities", "lbm_rates", "lbm_workspace_query",
-           "lbm_neighbor_table", "lbm_node_order", "raster_permutation", "SIGNATURES", "SETS", "STORAGE", "INDEX", "LIB_PATH"]
+           "lbm_neighbor_table", "lbm_node_order", "lbm_boundary_image", "raster_permutation", "SIGNATURES", "SETS", "STORAGE", "INDEX", "COLLISION", "WALL", "LIB_PATH"]

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -117,6 +118,10 @@ struct lbm_ctx {
     double g[3];
     int axis;
     int storage, index_kind;
+    int collision;
+    int wall_mode;      // LBM_WALL_HALFWAY or LBM_WALL_FULLWAY
+    float* wallbuf;     // full-way delay line (caller's workspace), state layout
+    int cus;
     lbm::RateClasses rates, ds_dtau, ds_dLambda;
     hipStream_t stream;
     char* ws;
@@ -151,6 +156,8 @@ hipError_t step_raw(lbm_ctx* c, const void* src, void* dst, double* partials,
                     const double* prev_partials = nullptr, double* prev_out = nullptr) {
     lbm::StepLaunch a{};
     a.storage = c->storage;
+    a.collision = c->collision;
+    a.wall = c->wall_mode == LBM_WALL_FULLWAY ? c->wallbuf : nullptr;
     a.src = src;
     a.dst = dst;
     a.idx = c->idx;
@@ -167,6 +174,25 @@ hipError_t step_raw(lbm_ctx* c, const void* src, void* dst, double* partials,
     a.prev_partials = prev_partials;
     a.prev_out = prev_out;
     return lbm::launch_step(a, c->stream);
+}
+
+// One resident wave of blocks: every block starts at once and walks the
+// chunk list with stride `grid` (a multiple of the XCD count when >= 64).
+hipError_t choose_grid(lbm_ctx* c) {
+    int per_cu = 0;
+    hipError_t he = lbm::step_occupancy(c->storage, c->index_kind, c->collision, &per_cu);
+    if (he != hipSuccess) return he;
+    const int64_t chunks = (c->nf + 255) / 256;
+    int64_t G = std::min<int64_t>(chunks, (int64_t)std::max(c->cus, 1) * std::max(per_cu, 1));
+    if (G >= 64) G -= G % 8;
+    c->grid = (int)std::min<int64_t>(G, kMaxGrid);
+    return hipSuccess;
+}
+
+// The rates form a two-relaxation-time set: one rate on every even
+// non-conserved moment (e, eps, p, pi) and one on every odd one (q, m).
+bool two_rate(const lbm::RateClasses& r) {
+    return r.s_e == r.s_nu && r.s_eps == r.s_nu && r.s_pi == r.s_nu && r.s_m == r.s_q;
 }
 
 double* slot(lbm_ctx* c, int64_t step_index) { return c->ring + (step_index % kRing) * 4; }
@@ -270,6 +296,33 @@ int lbm_node_order(const uint8_t* geometry, int nx, int ny, int nz, int64_t* vox
     return LBM_OK;
 }
 
+int lbm_boundary_dims(int nx, int ny, int nz, int pad, int mirror_y, int mirror_z, int* onx, int* ony,
+                      int* onz) {
+    std::string e = lbm::check_dims(nx, ny, nz);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    if (pad < 0 || pad > (1 << 20)) return fail(LBM_EINVAL, "pad must be in [0, 2^20]");
+    if (!onx || !ony || !onz) return fail(LBM_EINVAL, "NULL argument");
+    const int64_t ox = (int64_t)nx + 2 * (int64_t)pad, oy = mirror_y ? 2 * (int64_t)ny : ny,
+                  oz = mirror_z ? 2 * (int64_t)nz : nz;
+    if (ox > INT32_MAX || oy > INT32_MAX || oz > INT32_MAX) return fail(LBM_ERANGE, "extents overflow int");
+    e = lbm::check_dims((int)ox, (int)oy, (int)oz);
+    if (!e.empty()) return fail(LBM_ERANGE, e);
+    *onx = (int)ox;
+    *ony = (int)oy;
+    *onz = (int)oz;
+    return LBM_OK;
+}
+
+int lbm_boundary_image(const uint8_t* geometry, int nx, int ny, int nz, int pad, int mirror_y, int mirror_z,
+                       uint8_t* out) {
+    if (!geometry || !out) return fail(LBM_EINVAL, "NULL argument");
+    int ox, oy, oz;
+    int rc = lbm_boundary_dims(nx, ny, nz, pad, mirror_y, mirror_z, &ox, &oy, &oz);
+    if (rc) return rc;
+    lbm::boundary_image(geometry, nx, ny, nz, pad, mirror_y != 0, mirror_z != 0, out);
+    return LBM_OK;
+}
+
 int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
               double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
               void* workspace, size_t workspace_bytes, void* hip_stream) {
@@ -329,23 +382,20 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     c->exponent = (storage == LBM_F16 && gmax > 0) ? (int)std::lround(-std::log2(gmax)) - 4 : 0;
     if (c->exponent < 0) c->exponent = 0;
 
-    int dev = 0, cus = 0;
+    c->collision = LBM_COLLIDE_MRT;
+    c->wall_mode = LBM_WALL_HALFWAY;
+    c->wallbuf = nullptr;
+    int dev = 0;
+    c->cus = 0;
     auto cleanup = [&](int code) {
         delete c;
         return code;
     };
     hipError_t he = hipGetDevice(&dev);
-    if (he == hipSuccess) he = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (he == hipSuccess) he = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("device query: ") + hipGetErrorString(he)));
-    // One resident wave of blocks: every block starts at once and walks the
-    // chunk list with stride `grid` (rounded to a multiple of the XCD count).
-    int per_cu = 0;
-    if (he == hipSuccess) he = lbm::step_occupancy(storage, index_kind, &per_cu);
+    he = choose_grid(c);
     if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("occupancy query: ") + hipGetErrorString(he)));
-    const int64_t chunks = (nf + 255) / 256;
-    int64_t G = std::min<int64_t>(chunks, (int64_t)std::max(cus, 1) * std::max(per_cu, 1));
-    if (G >= 64) G -= G % 8;
-    c->grid = (int)std::min<int64_t>(G, kMaxGrid);
 
     lbm::IndexView& v = c->idx;
     v.kind = index_kind;
@@ -521,6 +571,8 @@ int lbm_set_state(lbm_ctx* c, const double* f) {
         }
     }
     HIP_TRY(hipMemcpyAsync(c->cur, raw.data(), raw.size(), hipMemcpyHostToDevice, c->stream));
+    if (c->wall_mode == LBM_WALL_FULLWAY)  // the state one step older starts equal to it
+        HIP_TRY(hipMemcpyAsync(c->wallbuf, c->cur, raw.size(), hipMemcpyDeviceToDevice, c->stream));
     HIP_TRY(lbm::launch_zero(c->ring, (int64_t)kRing * 4 * 8, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->steps = 0;
@@ -537,6 +589,52 @@ int lbm_fluid_index(lbm_ctx* c, int64_t* voxel) {
 int lbm_set_force_field(lbm_ctx* c, const float* g_device) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     c->field = g_device;
+    return LBM_OK;
+}
+
+int lbm_set_collision(lbm_ctx* c, int collision) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (collision != LBM_COLLIDE_MRT && collision != LBM_COLLIDE_TRT)
+        return fail(LBM_EINVAL, "collision must be LBM_COLLIDE_MRT or LBM_COLLIDE_TRT");
+    if (collision == LBM_COLLIDE_TRT && !two_rate(c->rates))
+        return fail(LBM_EINVAL, "the link-wise TRT collision needs a two-rate set (SRT, Set B or Set E)");
+    if (c->pending) {
+        int rc = flush(c);  // the pending partials were written with the current grid
+        if (rc) return rc;
+    }
+    const int old = c->collision, old_grid = c->grid;
+    c->collision = collision;
+    hipError_t he = choose_grid(c);
+    if (he != hipSuccess) {
+        c->collision = old;
+        c->grid = old_grid;
+        return fail(LBM_EHIP, std::string("occupancy query: ") + hipGetErrorString(he));
+    }
+    return LBM_OK;
+}
+
+int lbm_wall_workspace_query(lbm_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return fail(LBM_EINVAL, "NULL argument");
+    *bytes = align256((size_t)19 * c->np * 4);
+    return LBM_OK;
+}
+
+int lbm_set_wall(lbm_ctx* c, int mode, void* workspace, size_t workspace_bytes) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (mode == LBM_WALL_HALFWAY) {
+        c->wall_mode = mode;
+        c->wallbuf = nullptr;
+        return LBM_OK;
+    }
+    if (mode != LBM_WALL_FULLWAY) return fail(LBM_EINVAL, "mode must be LBM_WALL_HALFWAY or LBM_WALL_FULLWAY");
+    if (c->storage != LBM_F32) return fail(LBM_EINVAL, "full-way bounce-back needs FP32 storage");
+    const size_t need = align256((size_t)19 * c->np * 4);
+    if (!workspace || ((uintptr_t)workspace & 255)) return fail(LBM_EWORKSPACE, "wall workspace NULL or not 256-byte aligned");
+    if (workspace_bytes < need) return fail(LBM_EWORKSPACE, "wall workspace too small: need " + std::to_string(need));
+    c->wallbuf = static_cast<float*>(workspace);
+    // the state one step older than the current one starts equal to it
+    HIP_TRY(hipMemcpyAsync(c->wallbuf, c->cur, (size_t)19 * c->np * 4, hipMemcpyDeviceToDevice, c->stream));
+    c->wall_mode = mode;
     return LBM_OK;
 }
 
@@ -591,6 +689,7 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
                 double* dk_dtau, double* dk_dLambda, double* dk_dg) {
     if (!c || !dk_dtau || !dk_dLambda || !dk_dg) return fail(LBM_EINVAL, "NULL argument");
     if (c->storage != LBM_F32) return fail(LBM_EINVAL, "the adjoint needs FP32 storage");
+    if (c->wall_mode != LBM_WALL_HALFWAY) return fail(LBM_EINVAL, "the adjoint is built for halfway bounce-back");
     if (N < 1 || K < 1) return fail(LBM_EINVAL, "need n_steps >= 1 and checkpoint_every >= 1");
     if (c->g[c->axis] == 0) return fail(LBM_EINVAL, "no body force");
     const AdjLayout A = adj_layout(c, N, K);

@@ -279,6 +279,24 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
     });
 }
 
+void boundary_image(const uint8_t* g, int nx, int ny, int nz, int pad, bool mirror_y, bool mirror_z,
+                    uint8_t* out) {
+    const int ox = nx + 2 * pad, oy = mirror_y ? 2 * ny : ny, oz = mirror_z ? 2 * nz : nz;
+    parallel_slabs(oz, (int64_t)ox * oy * oz, [&](int z0, int z1) {
+        for (int z = z0; z < z1; ++z) {
+            const int sz = z < nz ? z : 2 * nz - 1 - z;   // reflected copy beyond the z face
+            for (int y = 0; y < oy; ++y) {
+                const int sy = y < ny ? y : 2 * ny - 1 - y;
+                uint8_t* row = out + ((int64_t)z * oy + y) * ox;
+                const uint8_t* src = g + ((int64_t)sz * ny + sy) * nx;
+                for (int x = 0; x < pad; ++x) row[x] = 0;
+                for (int x = 0; x < nx; ++x) row[pad + x] = src[x];
+                for (int x = pad + nx; x < ox; ++x) row[x] = 0;
+            }
+        }
+    });
+}
+
 void fluid_voxels(const uint8_t* g, int nx, int ny, int nz, int64_t* out) {
     auto start = row_starts(g, nx, ny, nz);
     parallel_slabs(nz, (int64_t)nx * ny * nz, [&](int z0, int z1) {

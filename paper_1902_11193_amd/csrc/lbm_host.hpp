@@ -101,6 +101,14 @@ struct BitmapIndex {
 };
 void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out);
 
+// Non-periodic image stacks (Sec. 2.2): `pad` fluid-only layers before and
+// after the image along x, then the image reflected across its y and/or z
+// faces, so that those faces become symmetry (mirror) planes of the periodic
+// box.  out is [nz'][ny'][nx'] with nx' = nx + 2 pad, ny' = ny (x2 when
+// mirror_y), nz' = nz (x2 when mirror_z).
+void boundary_image(const uint8_t* geom, int nx, int ny, int nz, int pad, bool mirror_y, bool mirror_z,
+                    uint8_t* out);
+
 // Linear voxel id x + nx (y + ny z) of every fluid node, in node order.
 void fluid_voxels(const uint8_t* geom, int nx, int ny, int nz, int64_t* out);
 

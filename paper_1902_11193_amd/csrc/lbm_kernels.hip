@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 
 namespace lbm {
@@ -390,6 +391,58 @@ __device__ __forceinline__ Mom collide_increment(const Mom& m, float jx, float j
     return h;
 }
 
+// ------------------------------------------------------------------ TRT
+// Two-relaxation-time collision (Sec. 2.1.2) applied link-wise, for two-rate
+// sets (SRT, B, E): every even non-conserved moment relaxes at sp = s_nu and
+// every odd one at sm = s_q.  Per opposite pair (a, b = opp(a)) the symmetric
+// part (f_a + f_b)/2 relaxes towards that of the incompressible equilibrium
+// e_a = w_a [drho + 3 c.j + 9/2 (c.j)^2 - 3/2 j.j] and gains (1 - sp/2) times
+// that of Guo's source w_a [3 (c - u).F + 9 (c.u)(c.F)]; the antisymmetric
+// part does the same at sm.  With the shifted j in the equilibrium this is the
+// MRT collision of those rates: the momentum gets sm F/2 from the relaxation
+// and (1 - sm/2) F from the source.  f holds deviations f - w rho0 on entry
+// and exit; returns the shifted momentum and drho for the reduction.
+struct TrtOut {
+    float jx, jy, jz, rho;
+};
+__device__ __forceinline__ TrtOut collide_trt(float f[19], float Fx, float Fy, float Fz, float sp,
+                                              float sm) {
+    float S[10], D[10];
+    unroll<9>([&](auto k) {
+        constexpr int a = 2 * decltype(k)::value + 1;
+        S[a >> 1] = f[a] + f[a + 1];
+        D[a >> 1] = f[a] - f[a + 1];
+    });
+    // pairs: 0 x, 1 y, 2 z, 3 (1,1,0), 4 (1,-1,0), 5 (1,0,1), 6 (1,0,-1), 7 (0,1,1), 8 (0,1,-1)
+    const float rho = f[0] + ((S[0] + S[1] + S[2]) + ((S[3] + S[4]) + (S[5] + S[6]) + (S[7] + S[8])));
+    const float jx = D[0] + (D[3] + D[4]) + (D[5] + D[6]) + 0.5f * Fx;
+    const float jy = D[1] + (D[3] - D[4]) + (D[7] + D[8]) + 0.5f * Fy;
+    const float jz = D[2] + (D[5] - D[6]) + (D[7] - D[8]) + 0.5f * Fz;
+    const float jj = jx * jx + jy * jy + jz * jz, uF = jx * Fx + jy * Fy + jz * Fz;
+    const float gp = 1.f - 0.5f * sp, gm = 1.f - 0.5f * sm;
+    const float A0 = sp * (rho - 1.5f * jj) - 3.f * gp * uF;   // per-node part of the symmetric update
+    const float a1 = 0.5f * (1.f - sp), a2 = 0.5f * (1.f - sm), c45 = 4.5f * sp, g9 = 9.f * gp;
+    f[0] = (1.f - sp) * f[0] + (1.f / 3.f) * A0;
+    auto pair = [&](int a, float w, float cj, float cF) {
+        const float P = (c45 * cj + g9 * cF) * cj + A0;
+        const float hp = a1 * S[a >> 1] + w * P;
+        const float hm = a2 * D[a >> 1] + 3.f * w * (sm * cj + gm * cF);
+        f[a] = hp + hm;
+        f[a + 1] = hp - hm;
+    };
+    constexpr float w1 = 1.f / 18.f, w2 = 1.f / 36.f;
+    pair(1, w1, jx, Fx);
+    pair(3, w1, jy, Fy);
+    pair(5, w1, jz, Fz);
+    pair(7, w2, jx + jy, Fx + Fy);
+    pair(9, w2, jx - jy, Fx - Fy);
+    pair(11, w2, jx + jz, Fx + Fz);
+    pair(13, w2, jx - jz, Fx - Fz);
+    pair(15, w2, jy + jz, Fy + Fz);
+    pair(17, w2, jy - jz, Fy - Fz);
+    return TrtOut{jx, jy, jz, rho};
+}
+
 // ------------------------------------------------------------------ reductions
 template <int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
@@ -440,12 +493,29 @@ k_finalize(const double* __restrict__ partials, int grid, double* __restrict__ o
 }
 
 // ------------------------------------------------------------------ step
-template <class C, class Ix, bool FIELD>
+// Wall links of a node as a bit mask (bit i: the voxel at x - c_i is solid).
+__device__ __forceinline__ uint32_t wall_bits(const int32_t s[19]) {
+    uint32_t b = 0;
+    unroll<18>([&](auto k) {
+        constexpr int i = decltype(k)::value + 1;
+        b |= (uint32_t)(s[i] < 0) << i;
+    });
+    return b;
+}
+
+// FW: full-way bounce-back (Sec. 2.2).  A population sent into a wall comes
+// back one step later than with the halfway wall, so at a wall link the node
+// takes fh_opp(i) of two steps ago.  `wall` keeps, per node and population p,
+// the fh_p this node had one step ago (same layout as a state): at a wall link
+// in direction i the node reads slot opp(i) there and writes back the fh_opp(i)
+// the halfway gather brought (the previous step's); only the node itself
+// touches its slots.
+template <class C, class Ix, bool FIELD, bool TRT, bool FW>
 __global__ void __launch_bounds__(kThreads)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
        uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
        const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
-       const double* __restrict__ prev_partials, double* __restrict__ prev_out) {
+       const double* __restrict__ prev_partials, double* __restrict__ prev_out, float* __restrict__ wall) {
     using T = typename C::T;
     // The previous step's block partials are reduced here, by the first block,
     // so a time step is a single launch; kernel order makes them visible.
@@ -468,6 +538,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
         uint32_t n = node_of(c), n1 = node_of(c + G);
         typename Ix::Pre pre1 = ix.prefetch(n1);
         uint32_t off[19];
+        uint32_t wb = 0;  // wall links of node n (FW only)
         {
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
@@ -475,6 +546,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             int32_t s[19];
             ix.sources(raw, p0, s);
             gather_offsets<T>(s, n, c, slack, off);
+            if constexpr (FW) wb = wall_bits(s);
         }
         for (;;) {
             // (1) index loads of the next node, (2) population loads of this
@@ -490,12 +562,23 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
                 constexpr int i = decltype(k)::value;
                 fr[i] = ld_off(gb, off[i]);
             });
+            float wv[19];
+            float* wc = FW ? wall + (size_t)c * kChunkElems : nullptr;
+            const uint32_t own = (n & (kThreads - 1u)) * 4u;
+            if constexpr (FW) {
+                unroll<18>([&](auto k) {
+                    constexpr int i = decltype(k)::value + 1;
+                    wv[i] = ld_off(wc + opp(i) * kThreads, own);
+                });
+            }
             const typename Ix::Pre pre2 = ix.prefetch(node_of(c + 2 * G));
             __builtin_amdgcn_sched_barrier(0);
+            const uint32_t wb_n = wb;
             {
                 int32_t s[19];
                 ix.sources(raw, pre1, s);
                 gather_offsets<T>(s, n1, c + G, slack, off);
+                if constexpr (FW) wb = wall_bits(s);
             }
             __builtin_amdgcn_sched_barrier(0);
             float f[19];
@@ -503,15 +586,41 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
                 constexpr int i = decltype(k)::value;
                 f[i] = C::cvt(fr[i], inv);
             });
+            if constexpr (FW) {
+                // wall link i: use the value of two steps ago, keep this one
+                unroll<18>([&](auto k) {
+                    constexpr int i = decltype(k)::value + 1;
+                    const bool w = (wb_n >> i) & 1u;
+                    const float halfway = f[i];
+                    f[i] = w ? wv[i] : halfway;
+                    wv[i] = w ? halfway : wv[i];
+                });
+                unroll<18>([&](auto k) {
+                    constexpr int i = decltype(k)::value + 1;
+                    st_off(wc + opp(i) * kThreads, own, wv[i]);
+                });
+            }
             float Fx = Fx0, Fy = Fy0, Fz = Fz0;
             if (FIELD) {
                 Fx = field[n];
                 Fy = field[nf + n];
                 Fz = field[2 * nf + n];
             }
-            const Mom m = moments(f);
-            const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
-            add_back(f, collide_increment(m, jx, jy, jz, Fx, Fy, Fz, r));
+            float jx, jy, jz, drho;
+            if constexpr (TRT) {
+                const TrtOut o = collide_trt(f, Fx, Fy, Fz, r.s_nu, r.s_q);
+                jx = o.jx;
+                jy = o.jy;
+                jz = o.jz;
+                drho = o.rho;
+            } else {
+                const Mom m = moments(f);
+                jx = m.jx + 0.5f * Fx;
+                jy = m.jy + 0.5f * Fy;
+                jz = m.jz + 0.5f * Fz;
+                drho = m.rho;
+                add_back(f, collide_increment(m, jx, jy, jz, Fx, Fy, Fz, r));
+            }
             // Lanes past the list carry n = nf - 1: they recompute that node
             // from the same inputs and store the same values, so the stores
             // stay unconditional (no branch for the compiler to sink the
@@ -520,7 +629,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             acc[0] += live * (double)jx;
             acc[1] += live * (double)jy;
             acc[2] += live * (double)jz;
-            acc[3] += live * (double)m.rho;
+            acc[3] += live * (double)drho;
             T* db = dst + (size_t)c * kChunkElems;
             unroll<19>([&](auto k) {
                 constexpr int i = decltype(k)::value;
@@ -735,26 +844,47 @@ BitmapIdx bitmap_view(const IndexView& v) {
                      (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by};
 }
 
-template <class C, class Ix>
-hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
+template <class C, class Ix, bool TRT, bool FW>
+hipError_t step_launch(const StepLaunch& a, Ix ix, hipStream_t s) {
     using T = typename C::T;
     const T* src = static_cast<const T*>(a.src);
     T* dst = static_cast<T*>(a.dst);
     if (a.field)
-        hipLaunchKernelGGL((k_step<C, Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
+        hipLaunchKernelGGL((k_step<C, Ix, true, TRT, FW>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
                            (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
-                           a.inv_scale, a.partials, a.prev_partials, a.prev_out);
+                           a.inv_scale, a.partials, a.prev_partials, a.prev_out, a.wall);
     else
-        hipLaunchKernelGGL((k_step<C, Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
+        hipLaunchKernelGGL((k_step<C, Ix, false, TRT, FW>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
                            ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
-                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.prev_out);
+                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.prev_out, a.wall);
     return hipGetLastError();
 }
 
-template <class C>
+// Full-way bounce-back is built for FP32 storage only.
+template <class C, class Ix, bool TRT>
+hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
+    if constexpr (std::is_same<C, CodecF32>::value) {
+        if (a.wall) return step_launch<C, Ix, TRT, true>(a, ix, s);
+    } else {
+        if (a.wall) return hipErrorInvalidValue;
+    }
+    return step_launch<C, Ix, TRT, false>(a, ix, s);
+}
+
+template <class C, bool TRT>
 hipError_t step_codec(const StepLaunch& a, hipStream_t s) {
-    if (a.idx.kind == kTable) return step_with<C>(a, table_view(a.idx), s);
-    return step_with<C>(a, bitmap_view(a.idx), s);
+    if (a.idx.kind == kTable) return step_with<C, TableIdx, TRT>(a, table_view(a.idx), s);
+    return step_with<C, BitmapIdx, TRT>(a, bitmap_view(a.idx), s);
+}
+
+template <bool TRT>
+hipError_t step_collision(const StepLaunch& a, hipStream_t s) {
+    switch (a.storage) {
+        case kF32: return step_codec<CodecF32, TRT>(a, s);
+        case kF16: return step_codec<CodecF16, TRT>(a, s);
+        case kBF16: return step_codec<CodecBF16, TRT>(a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 template <class Ix>
@@ -773,27 +903,28 @@ hipError_t adjoint_with(const AdjLaunch& a, Ix ix, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_step(const StepLaunch& a, hipStream_t s) {
-    switch (a.storage) {
-        case kF32: return step_codec<CodecF32>(a, s);
-        case kF16: return step_codec<CodecF16>(a, s);
-        case kBF16: return step_codec<CodecBF16>(a, s);
-    }
-    return hipErrorInvalidValue;
+    return a.collision == kTrt ? step_collision<true>(a, s) : step_collision<false>(a, s);
 }
 
-hipError_t step_occupancy(int storage, int index_kind, int* blocks_per_cu) {
+hipError_t step_occupancy(int storage, int index_kind, int collision, int* blocks_per_cu) {
     auto q = [&](const void* k) {
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k, kThreads, 0);
     };
-#define LBM_OCC(C, I) q(reinterpret_cast<const void*>(&k_step<C, I, false>))
-    if (index_kind == kTable) {
-        if (storage == kF32) return LBM_OCC(CodecF32, TableIdx);
-        if (storage == kF16) return LBM_OCC(CodecF16, TableIdx);
-        return LBM_OCC(CodecBF16, TableIdx);
+#define LBM_OCC(C, I, R) q(reinterpret_cast<const void*>(&k_step<C, I, false, R, false>))
+#define LBM_OCC2(R)                                                     \
+    if (index_kind == kTable) {                                         \
+        if (storage == kF32) return LBM_OCC(CodecF32, TableIdx, R);     \
+        if (storage == kF16) return LBM_OCC(CodecF16, TableIdx, R);     \
+        return LBM_OCC(CodecBF16, TableIdx, R);                         \
+    }                                                                   \
+    if (storage == kF32) return LBM_OCC(CodecF32, BitmapIdx, R);        \
+    if (storage == kF16) return LBM_OCC(CodecF16, BitmapIdx, R);        \
+    return LBM_OCC(CodecBF16, BitmapIdx, R);
+    if (collision == kTrt) {
+        LBM_OCC2(true)
     }
-    if (storage == kF32) return LBM_OCC(CodecF32, BitmapIdx);
-    if (storage == kF16) return LBM_OCC(CodecF16, BitmapIdx);
-    return LBM_OCC(CodecBF16, BitmapIdx);
+    LBM_OCC2(false)
+#undef LBM_OCC2
 #undef LBM_OCC
 }
 

@@ -10,6 +10,7 @@ namespace lbm {
 
 enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 enum IndexKind : int { kTable = 0, kBitmap = 1 };
+enum Collision : int { kMrt = 0, kTrt = 1 };
 
 struct RatesF {
     float s_e, s_eps, s_q, s_nu, s_pi, s_m;
@@ -28,6 +29,7 @@ struct IndexView {
 
 struct StepLaunch {
     int storage;
+    int collision;        // kMrt: moment space, any set; kTrt: link-wise, two-rate sets only
     const void* src;      // deviations (storage type), chunked: element (i, n) at state_elem(i, n)
     void* dst;            // same layout
     IndexView idx;
@@ -40,14 +42,16 @@ struct StepLaunch {
     double* partials;     // [grid][4] written by this step
     const double* prev_partials;  // [grid][4] of the previous step, reduced by block 0 ...
     double* prev_out;             // ... into prev_out[0..3]; nullptr: nothing pending
+    float* wall;          // full-way bounce-back: per-node fh of the previous step (state layout,
+                          // FP32 storage only), or nullptr for halfway bounce-back
 };
 
 // One fused step: gather with halfway bounce-back, MRT + Guo collision, store,
 // and per-block FP64 partial sums of (ux, uy, uz, drho).
 hipError_t launch_step(const StepLaunch& a, hipStream_t s);
 
-// Resident blocks per compute unit of the step kernel for this storage/index.
-hipError_t step_occupancy(int storage, int index_kind, int* blocks_per_cu);
+// Resident blocks per compute unit of the step kernel for this storage/index/collision.
+hipError_t step_occupancy(int storage, int index_kind, int collision, int* blocks_per_cu);
 
 // Sum the per-block partials in fixed order into out[0..3].
 hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s);

@@ -191,3 +191,25 @@ def test_gather_span_bounds_brute_force(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "bad 0" in r.stdout
+
+
+@pytest.mark.parametrize("shape,pad,my,mz", [((3, 4, 5), 2, True, True), ((4, 3, 6), 5, False, True),
+                                             ((2, 5, 3), 0, True, False), ((3, 3, 3), 1, False, False)])
+def test_boundary_image_pads_and_mirrors(shape, pad, my, mz):
+    """Padding along x with fluid layers and reflection across the y / z faces
+    (symmetry planes), checked against numpy."""
+    m = random_mask(shape, 0.4, 7)
+    want = m
+    if my:
+        want = np.concatenate([want, want[:, ::-1]], axis=1)
+    if mz:
+        want = np.concatenate([want, want[::-1]], axis=0)
+    want = np.pad(want, ((0, 0), (0, 0), (pad, pad)))
+    assert np.array_equal(P.lbm_boundary_image(m, pad, my, mz), want)
+
+
+def test_boundary_image_rejects_bad_arguments():
+    m = random_mask((3, 3, 3), 0.4, 7)
+    with pytest.raises(P.LbmError) as e:
+        P.lbm_boundary_image(m, -1)
+    assert e.value.code == P.LBM_EINVAL

@@ -1,0 +1,106 @@
+"""GPU parity of the non-periodic image boundaries (Sec. 2.2): full-way
+bounce-back against the oracle's full-way stream, and the padded / mirrored
+image (lbm_boundary_image) against the oracle's symmetry planes on the
+original image.  FP32 storage, 2e-6 of the deviation scale as in the other
+population tests."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1902_11193_amd as P
+from gpu_helpers import banner, dense_from_lib, lib_from_dense, random_state, deviation_error
+from lbm_inputs import random_mask, sphere
+
+pytestmark = pytest.mark.gpu
+
+G = (1e-4, 5e-5, -2e-5)
+
+
+@pytest.mark.parametrize("name,make", [("rand8", lambda: random_mask((8, 8, 8), 0.3, 11)),
+                                       ("rand_ragged", lambda: random_mask((7, 9, 11), 0.35, 12)),
+                                       ("sphere16", lambda: sphere(16, (7.5, 7.5, 7.5), 4.0))])
+@pytest.mark.parametrize("index", ["table", "bitmap"])
+@pytest.mark.parametrize("collision", ["mrt", "trt"])
+def test_fullway_bounce_back_matches_oracle(name, make, index, collision):
+    mask = make()
+    banner(f"fullway {name} {index} {collision}")
+    s = P.Solver(mask, 0.9, 3 / 16, "E", G, "f32", index)
+    s.set_collision(collision)
+    s.set_wall("fullway")
+    f0 = random_state(s.n_fluid, 5)
+    s.set_state(f0)                     # the one-step-older state starts equal to it
+    f0 = s.get_state()
+    p = O.Problem(mask, 0.9, 3 / 16, "E", G, fullway=True, collision=collision)
+    d0 = dense_from_lib(p, f0)
+    fh = torch.stack([d0, d0.clone()])
+    done = 0
+    for n in (1, 2, 50):
+        s.step(n - done)
+        for _ in range(n - done):
+            fh, u = p.step(fh)
+        done = n
+        err = deviation_error(s.get_state(), lib_from_dense(p, fh[0]))
+        assert err < 2e-6, (name, index, n, err)
+        uo = p.mean_velocity(u).numpy()
+        assert np.allclose(s.mean_velocity(), uo, rtol=0, atol=1e-6 * np.abs(uo).max())
+    s.close()
+
+
+def test_fullway_steady_k_equals_halfway():
+    mask = random_mask((8, 8, 8), 0.3, 11)
+    banner("fullway steady k 8^3")
+    ks = []
+    for wall in ("halfway", "fullway"):
+        s = P.Solver(mask, 1.0, 3 / 16, "E", (1e-5, 0, 0), "f32", "bitmap")
+        s.set_wall(wall)
+        s.step(4000)
+        ks.append(float(s.history(2)[:, 0].mean()))   # two-step mean: immune to a period-2 mode
+        s.close()
+    assert abs(ks[1] / ks[0] - 1) < 1e-5, ks
+
+
+@pytest.mark.parametrize("pad,sym", [(0, "yz"), (2, "yz"), (3, "y"), (0, "z")])
+def test_mirrored_image_matches_oracle_symmetry_planes(pad, sym):
+    """The library on the padded, mirrored image (periodic) equals the oracle
+    with symmetry planes on the padded original, on the original quarter."""
+    mask = random_mask((6, 7, 9), 0.3, 21)
+    banner(f"mirror pad={pad} sym={sym}")
+    big = P.lbm_boundary_image(mask, pad, "y" in sym, "z" in sym)
+    padded = np.pad(mask, ((0, 0), (0, 0), (pad, pad)))
+    s = P.Solver(big, 0.9, 3 / 16, "E", (1e-4, 0, 0), "f32", "bitmap")
+    pbig = O.Problem(big, 0.9, 3 / 16, "E", (1e-4, 0, 0))        # only for the node-order map
+    p = O.Problem(padded, 0.9, 3 / 16, "E", (1e-4, 0, 0), symmetric=sym)
+    fh = p.initial()
+    nz, ny, _ = padded.shape
+    done = 0
+    for n in (1, 2, 50):
+        s.step(n - done)
+        for _ in range(n - done):
+            fh, u = p.step(fh)
+        done = n
+        got = dense_from_lib(pbig, s.get_state())[:, :nz, :ny, :]
+        ref = lib_from_dense(p, fh)
+        err = deviation_error(lib_from_dense(p, got), ref)
+        assert err < 2e-6, (pad, sym, n, err)
+        # the driven superficial velocity of the big box is that of the quarter
+        assert abs(float(s.mean_velocity()[0]) / float(p.mean_velocity(u)[0]) - 1) < 1e-5
+    s.close()
+
+
+def test_wall_mode_errors():
+    mask = random_mask((6, 6, 6), 0.3, 2)
+    banner("wall mode errors")
+    s = P.Solver(mask, 0.9, 3 / 16, "E", G, "f16", "bitmap")
+    with pytest.raises(P.LbmError) as e:
+        s.set_wall("fullway")
+    assert e.value.code == P.LBM_EINVAL
+    s.close()
+    s = P.Solver(mask, 0.9, 3 / 16, "E", (1e-5, 0, 0), "f32", "bitmap")
+    s.set_wall("fullway")
+    with pytest.raises(P.LbmError) as e:
+        s.adjoint(10, 5)
+    assert e.value.code == P.LBM_EINVAL
+    s.set_wall("halfway")
+    s.step(2)
+    s.close()
