@@ -29,7 +29,8 @@ Models for Micro-tomographic Pore-spaces", arXiv:1902.11193):
 * halfway bounce-back at solid voxels (Sec. 2.2, the wall midway between a
   fluid and a solid voxel) in a periodic box with a body force (Sec. 2.2);
   as options, the paper's full-way bounce-back and symmetry (mirror) planes
-  on the box faces (Sec. 2.2);
+  on the box faces (Sec. 2.2), and Zou-He pressure boundaries on the x faces
+  with k from the pressure drop (Sec. 2.2, 3.1, Eq. perm_calc);
 * the two-relaxation-time collision in velocity space (Sec. 2.1.2), the
   link-wise form of the MRT collision for two-rate sets (SRT, B, E);
 * the Darcy permeability k_j = nu <u_j> / g_j from the volume-averaged
@@ -309,6 +310,39 @@ def stream_general(fh: torch.Tensor, solid: torch.Tensor, lat: Lattice, symmetri
     return out
 
 
+def zou_he_pressure(f: torch.Tensor, lat: Lattice, rho_in: float, rho_out: float) -> torch.Tensor:
+    """Zou-He pressure boundaries on the x faces (Sec. 2.2, Sec. 3.1): at the
+    fluid voxels of the plane x = 0 the five populations with c_x = +1, and of
+    x = nx - 1 those with c_x = -1, come from outside the image; they are
+    rebuilt so that the density is the prescribed one, the transverse velocity
+    is zero, and the non-equilibrium parts of opposite populations along x
+    are equal, with the transverse momentum of the known populations cancelled
+    on the diagonals.  ``f``: gathered populations (19, nz, ny, nx), full
+    (not deviations), changed in place and returned."""
+    c = lat.c
+    cx = c[:, 0]
+    for plane, rho_b, sgn in ((0, rho_in, 1), (f.shape[-1] - 1, rho_out, -1)):
+        g = f[..., plane]                                   # (19, nz, ny)
+        known0 = [i for i in range(19) if cx[i] == 0]
+        back = [i for i in range(19) if cx[i] == -sgn]      # leaving the box through this face
+        ju = sgn * (rho_b - g[known0].sum(0) - 2.0 * g[back].sum(0))   # rho u_x, sign of x
+        ny_ = 0.5 * sum(float(c[i, 1]) * g[i] for i in known0)
+        nz_ = 0.5 * sum(float(c[i, 2]) * g[i] for i in known0)
+        for i in range(19):
+            if cx[i] != sgn:
+                continue
+            b = int(lat.opp[i])
+            cy, cz = float(c[i, 1]), float(c[i, 2])
+            if cy == 0 and cz == 0:
+                g[i] = g[b] + sgn * ju / 3.0
+            else:
+                # w = 1/36 diagonal: rho (c.u)/6 with u = (u_x, 0, 0), minus the
+                # transverse momentum of the in-plane populations
+                g[i] = g[b] + sgn * ju / 6.0 - cy * ny_ - cz * nz_
+        f[..., plane] = g
+    return f
+
+
 def macroscopic(f: torch.Tensor, F: torch.Tensor, lat: Lattice):
     """rho = sum f, shifted momentum j = sum f c + F/2, u = j / rho0."""
     m = lat.M @ f
@@ -394,13 +428,16 @@ class Problem:
 
     def __init__(self, mask: np.ndarray, tau: float, Lambda: float | None, rset: str,
                  g, g_field: np.ndarray | None = None, linear: bool = False, collision: str = "mrt",
-                 symmetric: str = "", fullway: bool = False):
+                 symmetric: str = "", fullway: bool = False, pressure=None):
         self.lat = Lattice.make()
+        # Zou-He pressure boundaries on the x faces, (rho_in, rho_out): the box
+        # is then not periodic in x and k follows from the pressure drop
+        self.pressure = None if pressure is None else (float(pressure[0]), float(pressure[1]))
         # symmetry planes on the faces normal to the named axes (subset of "xyz"),
         # and full-way instead of halfway bounce-back (Sec. 2.2)
         self.symmetric = tuple(a in symmetric for a in "xyz")
         self.fullway = bool(fullway)
-        self.general = any(self.symmetric) or self.fullway
+        self.general = any(self.symmetric) or self.fullway or self.pressure is not None
         if collision not in ("mrt", "trt"):
             raise ValueError("collision must be 'mrt' or 'trt'")
         self.collision = collision
@@ -445,6 +482,8 @@ class Problem:
     def _step(self, fh, s, F, fh_wall=None):
         if self.general:
             f = stream_general(fh, self.solid, self.lat, self.symmetric, fh_wall)
+            if self.pressure is not None:
+                f = zou_he_pressure(f, self.lat, *self.pressure) * self.fluid.to(DT)[None]
         else:
             f = stream(fh, self.solid, self.lat)
         ff = f[:, self.fluid]
@@ -459,7 +498,14 @@ class Problem:
         return u.sum(1) / self.volume
 
     def permeability(self, umean: torch.Tensor) -> torch.Tensor:
-        """k_j = nu <u_j> / g_j (Eq. perm_calc with the pressure gradient dropped)."""
+        """k_j = nu <u_j> / g_j (Eq. perm_calc with the pressure gradient dropped);
+        with pressure boundaries k_x = nu <u_x> / grad p, grad p = c_s^2 (rho_in -
+        rho_out) / (nx - 1) between the boundary planes (Eq. perm_calc, rho0 = 1)."""
+        if self.pressure is not None:
+            gp = (self.pressure[0] - self.pressure[1]) / 3.0 / (self.shape[-1] - 1)
+            out = torch.full_like(umean, float("nan"))
+            out[0] = self.nu * umean[0] / gp
+            return out
         return torch.where(self.g != 0, self.nu * umean / self.g,
                            torch.full_like(umean, float("nan")))
 
@@ -589,5 +635,5 @@ __all__ = [
     "rates", "viscosity", "Lattice", "stream", "macroscopic", "collide", "rest_state",
     "Problem", "run", "run_to_steady", "state_at_fluid", "gradients", "unit_darcy",
     "time_steps", "SETS", "MOMENT_NAMES", "RHO0", "trt_rates", "equilibrium", "collide_trt",
-    "EVEN_ROWS", "ODD_ROWS", "mirror", "stream_general",
+    "EVEN_ROWS", "ODD_ROWS", "mirror", "stream_general", "zou_he_pressure",
 ]

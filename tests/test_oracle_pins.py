@@ -488,3 +488,49 @@ def test_fullway_steady_state_equals_halfway():
         assert r["converged"]
         ks.append(float(r["k"][0]))
     assert abs(ks[1] / ks[0] - 1) < 1e-9
+
+
+# ---------------------------------------------------------------- Zou-He pressure boundaries (Sec. 2.2, 3.1)
+def test_zou_he_sets_density_and_zero_transverse_velocity():
+    lat = O.Lattice.make()
+    g = torch.Generator().manual_seed(6)
+    f = lat.w[:, None, None, None] * (1 + 0.01 * torch.randn((19, 3, 4, 5), generator=g, dtype=torch.float64))
+    rin, rout = 1.0003, 0.9996
+    f = O.zou_he_pressure(f, lat, rin, rout)
+    c = lat.c.to(torch.float64)
+    for plane, rho in ((0, rin), (4, rout)):
+        fp = f[..., plane]
+        assert torch.allclose(fp.sum(0), torch.full_like(fp.sum(0), rho), atol=1e-15)
+        for a in (1, 2):
+            assert float((c[:, a][:, None, None] * fp).sum(0).abs().max()) < 1e-16
+        # non-equilibrium bounce-back along x: f1 - f1eq = f2 - f2eq at (rho, (u_x, 0, 0))
+        ux = (c[:, 0][:, None, None] * fp).sum(0) / 1.0
+        j = torch.stack([ux, torch.zeros_like(ux), torch.zeros_like(ux)]).reshape(3, -1)
+        feq = O.equilibrium(lat.c, lat.w, torch.full_like(ux, rho).reshape(-1), j, linear=True)
+        neq = fp.reshape(19, -1) - feq
+        i = int(torch.nonzero((lat.c == torch.tensor([1, 0, 0])).all(1))[0])
+        assert float((neq[i] - neq[int(lat.opp[i])]).abs().max()) < 1e-15
+
+
+@pytest.mark.parametrize("nx", [12])
+def test_pressure_driven_slit_exact_at_lambda_quarter(nx):
+    """Zou-He inlet/outlet and halfway walls: at Lambda = 1/4 the pressure-driven
+    slit has the closed-form permeability, k from the pressure drop over nx - 1
+    (Eq. perm_calc)."""
+    H, Ly = 8, 10
+    p = O.Problem(slit(nx, Ly, 1, H), 0.8, 1 / 4, "E", (0, 0, 0), linear=True, pressure=(1 + 5e-5, 1 - 5e-5))
+    r = O.run_to_steady(p, 1e-13, 400000)
+    assert r["converged"]
+    assert abs(float(r["k"][0]) / _slit_k(H, Ly, 1 / 4) - 1) < 1e-9
+
+
+def test_pressure_driven_slit_error_falls_with_length():
+    """Away from Lambda = 1/4 the boundary planes leave an O(1/nx) error in k."""
+    H, Ly = 8, 10
+    err = []
+    for nx in (12, 24):
+        p = O.Problem(slit(nx, Ly, 1, H), 0.8, 1 / 12, "E", (0, 0, 0), linear=True, pressure=(1 + 5e-5, 1 - 5e-5))
+        r = O.run_to_steady(p, 1e-13, 400000)
+        err.append(abs(float(r["k"][0]) / _slit_k(H, Ly, 1 / 12) - 1))
+    assert err[0] < 2e-3
+    assert abs(err[1] / err[0] - 0.5) < 0.05
