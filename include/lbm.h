@@ -197,7 +197,11 @@ int lbm_history(lbm_ctx* ctx, int count, double* u);
 /* Steps in chunks of `check_every` until the per-step relative change of
  * k along the largest |g| component falls below eps (Eq. convergence) or
  * max_steps have run.  *steps = steps taken in this call, k = last k,
- * *converged = 1 when the test held at some step of the last chunk. */
+ * *converged = 1 when the test held at some step of the last chunk.
+ * The test is the paper's, as printed: it can hold at a turning point of an
+ * early overshoot, and on geometries where k keeps a neutral period-2
+ * oscillation it may never hold; the mean of two successive lbm_history
+ * entries converges in that case. */
 int lbm_run_to_steady(lbm_ctx* ctx, double eps, int check_every, int max_steps, int* steps,
                       double k[3], int* converged);
 
@@ -235,6 +239,20 @@ int lbm_set_collision(lbm_ctx* ctx, int collision);
  * context in full-way mode. */
 int lbm_wall_workspace_query(lbm_ctx* ctx, size_t* bytes);
 int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes);
+
+/* Host only.  Pressure-driven flow (Sec. 2.2, 3.1): with enable != 0 the box
+ * is no longer periodic in x; the fluid nodes of the planes x = 0 and
+ * x = nx - 1 get Zou-He pressure boundaries at densities rho_in and rho_out
+ * (rho0 = 1): the populations arriving from outside the image are rebuilt
+ * from the known ones for that density, zero transverse velocity and equal
+ * non-equilibrium parts of the opposite pair along x.  lbm_permeability then
+ * returns k_x = nu <u_x> / grad p with grad p = (rho_in - rho_out) / 3 /
+ * (nx - 1) (Eq. perm_calc; k_y, k_z NaN), and lbm_run_to_steady tests k_x.
+ * Needs FP32 storage, the bitmap index, g = (0, 0, 0) at lbm_setup, no force
+ * field, halfway bounce-back and nx >= 3 (else LBM_EINVAL; rho_in, rho_out
+ * finite, positive, different).  enable = 0 returns to the periodic box.
+ * lbm_adjoint refuses a context with pressure faces. */
+int lbm_set_pressure(lbm_ctx* ctx, int enable, double rho_in, double rho_out);
 
 /* FP16 storage keeps 2^e (f_i - w_i rho0); e defaults to
  * round(-log2 max|g|) - 4.  May be changed at any time (the state is
