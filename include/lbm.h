@@ -32,8 +32,9 @@
  *     with weights 1/3, 1/18 (|c|^2 = 1), 1/36 (|c|^2 = 2); rho0 = 1.
  *   - State: post-collision populations after the last step.  On the device
  *     they are stored as deviations f_i - w_i rho0 in FP32, FP16 or BF16
- *     (FP16 scaled by a power of two); collision arithmetic is FP32; the mean
- *     velocity and mass are reduced in FP64.
+ *     (FP16 scaled by a power of two), or for LBM_F16R as FP16 deviations
+ *     from a per-node reference density (below); collision arithmetic is
+ *     FP32; the mean velocity and mass are reduced in FP64.
  *   - Step n = gather (pull stream with halfway bounce-back), then collide.
  *     <u>_n is the volume average (sum over fluid / (nx ny nz)) of the
  *     shifted velocity (sum_i f_i c_i + F/2) / rho0 of the populations
@@ -71,10 +72,20 @@ extern "C" {
 #define LBM_SET_D 4
 #define LBM_SET_E 5
 
-/* Storage type of the population deviations. */
+/* Storage type of the population deviations.
+ * LBM_F32, LBM_F16, LBM_BF16: f_i - w_i rho0 (FP16 scaled by 2^e).
+ * LBM_F16R: FP16 with a reference density per node.  A node also stores
+ *   r = fp16(rho - rho0) of its own populations, and each population as
+ *   2^e (f_i - w_i rho0 - w_i r); the node that pulls a value adds w_i r of
+ *   the node it came from.  Both sides use the same stored r, so nothing is
+ *   lost to the reference; FP16 rounds only the velocity and
+ *   non-equilibrium part.  In rock that part is orders of magnitude smaller
+ *   than the density deviation that plain FP16 must carry.  20 values per
+ *   node (80 bytes per node-update moved instead of 76). */
 #define LBM_F32 0
 #define LBM_F16 1
 #define LBM_BF16 2
+#define LBM_F16R 3
 
 /* Neighbour layout used by the gather.
  * LBM_INDEX_TABLE:  int32 [18][n_pad] table of pull-source nodes (-1 = wall),
@@ -127,7 +138,7 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
  * LBM_ERANGE: 2^31 or more fluid nodes; packed coordinates over 32 bits
  * (bitmap index); or the populations gathered around one 256-node chunk
  * spanning 4 GiB or more in the chosen storage (three 16-plane z-tiles of
- * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16). */
+ * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16, 40 for F16R). */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
 
@@ -255,8 +266,10 @@ int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes
 int lbm_set_pressure(lbm_ctx* ctx, int enable, double rho_in, double rho_out);
 
 /* FP16 storage keeps 2^e (f_i - w_i rho0); e defaults to
- * round(-log2 max|g|) - 4.  May be changed at any time (the state is
- * rescaled).  Ignored for FP32 / BF16 storage, where e = 0. */
+ * round(-log2 max|g|) - 4, and for LBM_F16R to round(-log2 max|g|) + 2
+ * (its values are velocity-sized).  May be changed at any time (the state is
+ * rescaled; LBM_F16R's reference slot is not scaled).  Ignored for FP32 /
+ * BF16 storage, where e = 0. */
 int lbm_set_storage_exponent(lbm_ctx* ctx, int e);
 
 /* Discrete adjoint (spec extension of the paper's method): exact

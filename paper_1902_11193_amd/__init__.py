@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOFLUID, LBM_EWORKSPACE, LBM_EHIP, LBM_ENAN, LBM_ERANGE = 0, -1, -2, -3, -4, -5, -6
 SETS = {"SRT": 0, "A": 1, "B": 2, "C": 3, "D": 4, "E": 5}
-STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "f16r": 3}
 INDEX = {"table": 0, "bitmap": 1}
 COLLISION = {"mrt": 0, "trt": 1}
 WALL = {"halfway": 0, "fullway": 1}
@@ -52,6 +52,7 @@ SIGNATURES = {
     "lbm_set_collision": (c_int, [c_void_p, c_int]),
     "lbm_wall_workspace_query": (c_int, [c_void_p, c_void_p]),
     "lbm_set_wall": (c_int, [c_void_p, c_int, c_void_p, c_size_t]),
+    "lbm_set_pressure": (c_int, [c_void_p, c_int, c_double, c_double]),
     "lbm_boundary_dims": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "lbm_boundary_image": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p]),
     "lbm_adjoint_workspace_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
@@ -263,6 +264,13 @@ class Solver:
     def set_collision(self, kind: str):
         """'mrt' (moment space, any set) or 'trt' (link-wise, SRT / B / E)."""
         _check(lib().lbm_set_collision(self._ctx, COLLISION[kind]))
+
+    def set_pressure(self, rho_in: float | None, rho_out: float | None = None):
+        """Zou-He pressure faces at x = 0 / nx - 1 with these densities; None: periodic again."""
+        if rho_in is None:
+            _check(lib().lbm_set_pressure(self._ctx, 0, 1.0, 1.0))
+        else:
+            _check(lib().lbm_set_pressure(self._ctx, 1, float(rho_in), float(rho_out)))
 
     def set_wall(self, kind: str):
         """'halfway' (default) or 'fullway' bounce-back (FP32 storage)."""

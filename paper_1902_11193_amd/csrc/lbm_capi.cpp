@@ -40,6 +40,8 @@ double weight(int i) {
 }
 
 size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
+// values kept per node: 19 populations, plus the reference density for LBM_F16R
+int slots(int storage) { return storage == LBM_F16R ? 20 : 19; }
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
@@ -51,7 +53,7 @@ struct Layout {
 Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int ny, int nz) {
     Layout L{};
     size_t off = 0;
-    const size_t state = align256((size_t)19 * np * elem_size(storage));
+    const size_t state = align256((size_t)slots(storage) * np * elem_size(storage));
     L.A = off;
     off += state;
     L.B = off;
@@ -79,7 +81,7 @@ std::string check_common(const uint8_t* geom, int nx, int ny, int nz, int storag
     if (!geom) return "geometry is NULL";
     std::string e = lbm::check_dims(nx, ny, nz);
     if (!e.empty()) return e;
-    if (storage < LBM_F32 || storage > LBM_BF16) return "storage must be LBM_F32, LBM_F16 or LBM_BF16";
+    if (storage < LBM_F32 || storage > LBM_F16R) return "storage must be LBM_F32, LBM_F16, LBM_BF16 or LBM_F16R";
     if (index_kind != LBM_INDEX_TABLE && index_kind != LBM_INDEX_BITMAP)
         return "index_kind must be LBM_INDEX_TABLE or LBM_INDEX_BITMAP";
     return "";
@@ -121,6 +123,8 @@ struct lbm_ctx {
     int collision;
     int wall_mode;      // LBM_WALL_HALFWAY or LBM_WALL_FULLWAY
     float* wallbuf;     // full-way delay line (caller's workspace), state layout
+    bool pressure;      // Zou-He pressure faces on x = 0 and x = nx - 1
+    double rho_in, rho_out;
     int cus;
     lbm::RateClasses rates, ds_dtau, ds_dLambda;
     hipStream_t stream;
@@ -158,6 +162,9 @@ hipError_t step_raw(lbm_ctx* c, const void* src, void* dst, double* partials,
     a.storage = c->storage;
     a.collision = c->collision;
     a.wall = c->wall_mode == LBM_WALL_FULLWAY ? c->wallbuf : nullptr;
+    a.pressure = c->pressure;
+    a.drho_in = (float)(c->rho_in - 1.0);
+    a.drho_out = (float)(c->rho_out - 1.0);
     a.src = src;
     a.dst = dst;
     a.idx = c->idx;
@@ -267,7 +274,7 @@ int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int sto
     if (nf >= ((int64_t)1 << 31) - 256) return fail(LBM_ERANGE, "more than 2^31 fluid nodes");
     if (index_kind == LBM_INDEX_BITMAP && !lbm::coord_bits(nx, ny, nz).fits())
         return fail(LBM_ERANGE, "packed voxel coordinates need more than 32 bits");
-    e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz), storage);
+    e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, slots(storage)), storage);
     if (!e.empty()) return fail(LBM_ERANGE, e);
     if (bytes) *bytes = layout(lbm::padded(nf), nf, storage, index_kind, nx, ny, nz).total;
     return LBM_OK;
@@ -377,14 +384,20 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     c->steps = 0;
     c->field = nullptr;
     c->geom.assign(geometry, geometry + (size_t)nx * ny * nz);
-    c->span = lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz);
+    c->span = lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, slots(storage));
     double gmax = std::max({std::fabs(g[0]), std::fabs(g[1]), std::fabs(g[2])});
-    c->exponent = (storage == LBM_F16 && gmax > 0) ? (int)std::lround(-std::log2(gmax)) - 4 : 0;
+    // FP16 scale: plain deviations hold the density deviation, which grows to
+    // ~1e2-1e3 g in rock; the referenced ones hold velocity-sized values only
+    c->exponent = 0;
+    if (storage == LBM_F16 && gmax > 0) c->exponent = (int)std::lround(-std::log2(gmax)) - 4;
+    if (storage == LBM_F16R && gmax > 0) c->exponent = (int)std::lround(-std::log2(gmax)) + 2;
     if (c->exponent < 0) c->exponent = 0;
 
     c->collision = LBM_COLLIDE_MRT;
     c->wall_mode = LBM_WALL_HALFWAY;
     c->wallbuf = nullptr;
+    c->pressure = false;
+    c->rho_in = c->rho_out = 1.0;
     int dev = 0;
     c->cus = 0;
     auto cleanup = [&](int code) {
@@ -462,6 +475,13 @@ int lbm_permeability(lbm_ctx* c, double k[3]) {
     double u[3];
     int rc = lbm_mean_velocity(c, u);
     if (rc) return rc;
+    if (c->pressure) {
+        // Eq. perm_calc: grad p = c_s^2 (rho_in - rho_out) / (nx - 1) between the faces
+        const double gp = (c->rho_in - c->rho_out) / 3.0 / (c->nx - 1);
+        k[0] = viscosity(c) * u[0] / gp;
+        k[1] = k[2] = NAN;
+        return LBM_OK;
+    }
     for (int a = 0; a < 3; ++a) k[a] = c->g[a] != 0 ? viscosity(c) * u[a] / c->g[a] : NAN;
     return LBM_OK;
 }
@@ -501,7 +521,7 @@ int lbm_run_to_steady(lbm_ctx* c, double eps, int check_every, int max_steps, in
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!(eps > 0) || check_every < 1 || check_every > kRing - 1 || max_steps < 0)
         return fail(LBM_EINVAL, "need eps > 0, 1 <= check_every < 1024, max_steps >= 0");
-    if (c->g[c->axis] == 0) return fail(LBM_EINVAL, "no body force");
+    if (c->g[c->axis] == 0 && !c->pressure) return fail(LBM_EINVAL, "no body force and no pressure drop");
     int done = 0, conv = 0;
     std::vector<double> h;
     while (done < max_steps && !conv) {
@@ -531,19 +551,23 @@ int lbm_run_to_steady(lbm_ctx* c, double eps, int check_every, int max_steps, in
 int lbm_get_state(lbm_ctx* c, double* f) {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
     const size_t es = elem_size(c->storage);
-    std::vector<char> raw((size_t)19 * c->np * es);
+    const int S = slots(c->storage);
+    std::vector<char> raw((size_t)S * c->np * es);
     HIP_TRY(hipMemcpyAsync(raw.data(), c->cur, raw.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     const double inv = 1.0 / std::ldexp(1.0, c->exponent);
+    const _Float16* h16 = reinterpret_cast<const _Float16*>(raw.data());
     for (int i = 0; i < 19; ++i) {
         const double w = weight(i);
         for (int64_t n = 0; n < c->nf; ++n) {
-            const size_t at = (size_t)lbm::state_elem(i, n);
+            const size_t at = (size_t)lbm::state_elem(i, n, S);
             double d;
             if (c->storage == LBM_F32)
                 d = reinterpret_cast<const float*>(raw.data())[at];
             else if (c->storage == LBM_F16)
-                d = (double)(float)reinterpret_cast<const _Float16*>(raw.data())[at] * inv;
+                d = (double)(float)h16[at] * inv;
+            else if (c->storage == LBM_F16R)
+                d = (double)((float)h16[at] * (float)inv + (float)w * (float)h16[lbm::state_elem(S - 1, n, S)]);
             else
                 d = (double)from_bf16(reinterpret_cast<const uint16_t*>(raw.data())[at]);
             f[(size_t)i * c->nf + n] = w + d;
@@ -555,17 +579,32 @@ int lbm_get_state(lbm_ctx* c, double* f) {
 int lbm_set_state(lbm_ctx* c, const double* f) {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
     const size_t es = elem_size(c->storage);
-    std::vector<char> raw((size_t)19 * c->np * es, 0);
+    const int S = slots(c->storage);
+    std::vector<char> raw((size_t)S * c->np * es, 0);
     const double sc = std::ldexp(1.0, c->exponent);
+    _Float16* h16 = reinterpret_cast<_Float16*>(raw.data());
+    std::vector<float> ref;
+    if (c->storage == LBM_F16R) {  // each node's reference: its density deviation in FP16
+        ref.resize(c->nf);
+        for (int64_t n = 0; n < c->nf; ++n) {
+            double d = -1.0;
+            for (int i = 0; i < 19; ++i) d += f[(size_t)i * c->nf + n];
+            const _Float16 r = (_Float16)(float)d;
+            h16[lbm::state_elem(S - 1, n, S)] = r;
+            ref[n] = (float)r;
+        }
+    }
     for (int i = 0; i < 19; ++i) {
         const double w = weight(i);
         for (int64_t n = 0; n < c->nf; ++n) {
-            const size_t at = (size_t)lbm::state_elem(i, n);
+            const size_t at = (size_t)lbm::state_elem(i, n, S);
             const double d = f[(size_t)i * c->nf + n] - w;
             if (c->storage == LBM_F32)
                 reinterpret_cast<float*>(raw.data())[at] = (float)d;
             else if (c->storage == LBM_F16)
-                reinterpret_cast<_Float16*>(raw.data())[at] = (_Float16)(float)(d * sc);
+                h16[at] = (_Float16)(float)(d * sc);
+            else if (c->storage == LBM_F16R)
+                h16[at] = (_Float16)(float)((d - w * (double)ref[n]) * sc);
             else
                 reinterpret_cast<uint16_t*>(raw.data())[at] = to_bf16((float)d);
         }
@@ -588,6 +627,7 @@ int lbm_fluid_index(lbm_ctx* c, int64_t* voxel) {
 
 int lbm_set_force_field(lbm_ctx* c, const float* g_device) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->pressure && g_device) return fail(LBM_EINVAL, "a force field cannot be combined with pressure faces");
     c->field = g_device;
     return LBM_OK;
 }
@@ -628,6 +668,7 @@ int lbm_set_wall(lbm_ctx* c, int mode, void* workspace, size_t workspace_bytes) 
     }
     if (mode != LBM_WALL_FULLWAY) return fail(LBM_EINVAL, "mode must be LBM_WALL_HALFWAY or LBM_WALL_FULLWAY");
     if (c->storage != LBM_F32) return fail(LBM_EINVAL, "full-way bounce-back needs FP32 storage");
+    if (c->pressure) return fail(LBM_EINVAL, "full-way bounce-back cannot be combined with pressure faces");
     const size_t need = align256((size_t)19 * c->np * 4);
     if (!workspace || ((uintptr_t)workspace & 255)) return fail(LBM_EWORKSPACE, "wall workspace NULL or not 256-byte aligned");
     if (workspace_bytes < need) return fail(LBM_EWORKSPACE, "wall workspace too small: need " + std::to_string(need));
@@ -638,12 +679,33 @@ int lbm_set_wall(lbm_ctx* c, int mode, void* workspace, size_t workspace_bytes) 
     return LBM_OK;
 }
 
+int lbm_set_pressure(lbm_ctx* c, int enable, double rho_in, double rho_out) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!enable) {
+        c->pressure = false;
+        return LBM_OK;
+    }
+    if (!std::isfinite(rho_in) || !std::isfinite(rho_out) || !(rho_in > 0) || !(rho_out > 0) || rho_in == rho_out)
+        return fail(LBM_EINVAL, "need finite, positive and different rho_in, rho_out");
+    if (c->storage != LBM_F32 || c->index_kind != LBM_INDEX_BITMAP)
+        return fail(LBM_EINVAL, "pressure faces need FP32 storage and the bitmap index");
+    if (c->g[0] != 0 || c->g[1] != 0 || c->g[2] != 0 || c->field)
+        return fail(LBM_EINVAL, "pressure faces need a context without body force");
+    if (c->wall_mode != LBM_WALL_HALFWAY) return fail(LBM_EINVAL, "pressure faces need halfway bounce-back");
+    if (c->nx < 3) return fail(LBM_EINVAL, "pressure faces need nx >= 3");
+    c->pressure = true;
+    c->rho_in = rho_in;
+    c->rho_out = rho_out;
+    c->axis = 0;
+    return LBM_OK;
+}
+
 int lbm_set_storage_exponent(lbm_ctx* c, int e) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-    if (c->storage != LBM_F16) return LBM_OK;
+    if (c->storage != LBM_F16 && c->storage != LBM_F16R) return LBM_OK;
     if (e < -60 || e > 60) return fail(LBM_EINVAL, "exponent out of range [-60, 60]");
     const float factor = std::ldexp(1.0f, e - c->exponent);
-    HIP_TRY(lbm::launch_rescale(c->storage, c->cur, (int64_t)19 * c->np, factor, c->stream));
+    HIP_TRY(lbm::launch_rescale(c->storage, c->cur, (int64_t)slots(c->storage) * c->np, factor, c->stream));
     c->exponent = e;
     return LBM_OK;
 }
@@ -690,6 +752,7 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
     if (!c || !dk_dtau || !dk_dLambda || !dk_dg) return fail(LBM_EINVAL, "NULL argument");
     if (c->storage != LBM_F32) return fail(LBM_EINVAL, "the adjoint needs FP32 storage");
     if (c->wall_mode != LBM_WALL_HALFWAY) return fail(LBM_EINVAL, "the adjoint is built for halfway bounce-back");
+    if (c->pressure) return fail(LBM_EINVAL, "the adjoint is built for the body-force-driven periodic box");
     if (N < 1 || K < 1) return fail(LBM_EINVAL, "need n_steps >= 1 and checkpoint_every >= 1");
     if (c->g[c->axis] == 0) return fail(LBM_EINVAL, "no body force");
     const AdjLayout A = adj_layout(c, N, K);

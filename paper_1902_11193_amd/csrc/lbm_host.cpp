@@ -163,14 +163,14 @@ std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
     return start;
 }
 
-GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz) {
+GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz, int S) {
     const int T = (nz + kNodeTileZ - 1) / kNodeTileZ;
     const int64_t total = start[(int64_t)ny * nz];
     // first node of the tile at each position, and one past its last
     std::vector<int64_t> first(T), last(T);
     for (int p = 0; p < T; ++p) first[p] = start[(int64_t)tile_at(p, T) * kNodeTileZ * ny];
     for (int p = 0; p < T; ++p) last[p] = p + 1 < T ? first[p + 1] : total;
-    const int64_t E = 19 * kChunk;
+    const int64_t E = (int64_t)S * kChunk;
     auto chunk_lo = [&](int64_t node) { return node / kChunk * E; };
     auto chunk_hi = [&](int64_t node) { return (node / kChunk + 1) * E; };
     GatherSpan g{0, 0};

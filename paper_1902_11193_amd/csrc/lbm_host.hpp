@@ -56,10 +56,10 @@ constexpr int kChunk = 256;
 inline int64_t padded(int64_t nf) { return (nf + kChunk - 1) / kChunk * kChunk; }
 
 // Population layout in device memory: the kChunk nodes of chunk q = n / kChunk
-// keep their 19 populations back to back, element (i, n) at
-// q * 19 * kChunk + i * kChunk + n % kChunk.
-inline int64_t state_elem(int i, int64_t n) {
-    return (n / kChunk) * (19 * kChunk) + (int64_t)i * kChunk + n % kChunk;
+// keep their S values back to back (S = 19 populations, or 20 with a
+// reference-density slot), element (i, n) at q * S * kChunk + i * kChunk + n % kChunk.
+inline int64_t state_elem(int i, int64_t n, int S = 19) {
+    return (n / kChunk) * ((int64_t)S * kChunk) + (int64_t)i * kChunk + n % kChunk;
 }
 
 // The step kernels address a chunk's gathers as 32-bit byte offsets from a
@@ -70,7 +70,7 @@ inline int64_t state_elem(int i, int64_t n) {
 struct GatherSpan {
     int64_t slack, reach;  // elements
 };
-GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz);
+GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz, int S = 19);
 
 // Pull-source table [18][stride], entry (i-1)*stride + n; -1 = solid source.
 void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_t stride,

@@ -39,6 +39,8 @@ __host__ __device__ constexpr int cdir(int i, int a) {
     return t[i][a];
 }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// lattice weights w_i: 1/3 rest, 1/18 axis (i = 1..6), 1/36 diagonal
+__host__ __device__ constexpr float wgt(int i) { return i == 0 ? 1.f / 3.f : (i <= 6 ? 1.f / 18.f : 1.f / 36.f); }
 
 template <class F, int... I>
 __device__ __forceinline__ void unroll_impl(F&& f, std::integer_sequence<int, I...>) {
@@ -54,16 +56,22 @@ __device__ __forceinline__ void unroll(F&& f) {
 // encodes one (FP16 carries a power-of-two scale; BF16 rounds to nearest even).
 struct CodecF32 {
     using T = float;
+    static constexpr int kSlots = 19;    // values kept per node
+    static constexpr bool kRef = false;  // populations stored relative to a reference density
     static __device__ __forceinline__ float cvt(T v, float) { return v; }
     static __device__ __forceinline__ T enc(float v, float) { return v; }
 };
 struct CodecF16 {
     using T = _Float16;
+    static constexpr int kSlots = 19;
+    static constexpr bool kRef = false;
     static __device__ __forceinline__ float cvt(T v, float inv) { return (float)v * inv; }
     static __device__ __forceinline__ T enc(float v, float s) { return (_Float16)(v * s); }
 };
 struct CodecBF16 {
     using T = uint16_t;
+    static constexpr int kSlots = 19;
+    static constexpr bool kRef = false;
     static __device__ __forceinline__ float cvt(T v, float inv) {
         return __uint_as_float((uint32_t)v << 16) * inv;
     }
@@ -72,6 +80,21 @@ struct CodecBF16 {
         if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
         return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);               // nearest even
     }
+};
+
+// FP16 relative to a per-node reference density: a node stores, besides its
+// populations, r = fp16(drho) in a 20th slot, and each population as
+// 2^e (f_i - w_i rho0 - w_i r).  A reader adds w_i r of the node the value
+// came from.  Writer and reader use the same stored r, so the reference is
+// exact; what FP16 rounds is only the velocity and non-equilibrium part,
+// not the density (pressure) deviation that dominates f - w rho0 in poorly
+// connected rock.
+struct CodecF16R {
+    using T = _Float16;
+    static constexpr int kSlots = 20;
+    static constexpr bool kRef = true;
+    static __device__ __forceinline__ float cvt(T v, float inv) { return (float)v * inv; }
+    static __device__ __forceinline__ T enc(float v, float s) { return (_Float16)(v * s); }
 };
 
 // ------------------------------------------------------------------ addressing
@@ -96,10 +119,12 @@ __device__ __forceinline__ void st_stream(T* base, uint32_t byte_off, T v) {
 
 // ------------------------------------------------------------------ layout
 // Element (i, m) of a population array sits at node_elem(m) + i * kThreads:
-// chunk q = m / 256 owns elements [q * 19 * 256, (q + 1) * 19 * 256).
+// chunk q = m / 256 owns elements [q * S * 256, (q + 1) * S * 256), S = 19
+// values per node (20 with a reference-density slot).
 constexpr uint32_t kChunkElems = 19u * kThreads;
+template <int S = 19>
 __device__ __forceinline__ uint32_t node_elem(uint32_t m) {
-    return m + (m >> 8) * (kChunkElems - kThreads);  // = (m / 256) * 19 * 256 + m % 256
+    return m + (m >> 8) * ((uint32_t)(S - 1) * kThreads);  // = (m / 256) * S * 256 + m % 256
 }
 
 // Gathers of one chunk go through a wave-uniform base pointer placed `slack`
@@ -107,37 +132,37 @@ __device__ __forceinline__ uint32_t node_elem(uint32_t m) {
 // lane; the host checks (gather_span) that every element a chunk gathers lies
 // within 2^32 bytes above that base.  Offsets are formed modulo 2^32, which
 // is exact for values that fit.
-template <class T>
+template <class T, int S = 19>
 __device__ __forceinline__ const T* chunk_base(const T* p, uint32_t chunk, uint32_t slack) {
-    return p + ((int64_t)chunk * kChunkElems - (int64_t)slack);
+    return p + ((int64_t)chunk * (S * kThreads) - (int64_t)slack);
 }
 // Byte offset, from the base of chunk cbe / kChunkElems, of the population
 // pulled in direction i: population i of the source node m, or, when the
 // source voxel is solid (m < 0), population opp(i) of the node itself (en =
 // node_elem of the node; halfway bounce-back).
-template <class T, int I>
+template <class T, int I, int S = 19>
 __device__ __forceinline__ uint32_t pull_offset(int32_t m, uint32_t en, uint32_t kb) {
     // both candidates, then a bitwise select: no branch per direction
-    const uint32_t pulled = node_elem((uint32_t)m) + (uint32_t)I * kThreads;
+    const uint32_t pulled = node_elem<S>((uint32_t)m) + (uint32_t)I * kThreads;
     const uint32_t own = en + (uint32_t)opp(I) * kThreads;
     const uint32_t wall = (uint32_t)(m >> 31);  // all ones when m < 0
     return ((pulled & ~wall) | (own & wall)) * (uint32_t)sizeof(T) + kb;
 }
 // kb of a chunk: (slack - first element of the chunk) * sizeof(T), mod 2^32
-template <class T>
+template <class T, int S = 19>
 __device__ __forceinline__ uint32_t chunk_kb(uint32_t chunk, uint32_t slack) {
-    return (slack - chunk * kChunkElems) * (uint32_t)sizeof(T);
+    return (slack - chunk * (uint32_t)(S * kThreads)) * (uint32_t)sizeof(T);
 }
 // Offsets of the 19 populations gathered into node n of chunk `chunk`
 // (off[0]: its own rest population) from the pull sources s.
-template <class T>
+template <class T, int S = 19>
 __device__ __forceinline__ void gather_offsets(const int32_t s[19], uint32_t n, uint32_t chunk,
                                                uint32_t slack, uint32_t off[19]) {
-    const uint32_t en = node_elem(n), kb = chunk_kb<T>(chunk, slack);
+    const uint32_t en = node_elem<S>(n), kb = chunk_kb<T, S>(chunk, slack);
     off[0] = en * (uint32_t)sizeof(T) + kb;
     unroll<18>([&](auto k) {
         constexpr int i = decltype(k)::value + 1;
-        off[i] = pull_offset<T, i>(s[i], en, kb);
+        off[i] = pull_offset<T, i, S>(s[i], en, kb);
     });
 }
 
@@ -210,6 +235,11 @@ struct BitmapIdx {
     }
     using Pre = uint32_t;  // the node's packed coordinate, loaded ahead of use
     __device__ __forceinline__ Pre prefetch(uint32_t n) const { return ld_off(coords, n * 4u); }
+    // 1 on the plane x = 0, 2 on x = nx - 1, else 0
+    __device__ __forceinline__ uint32_t x_face(Pre c) const {
+        const uint32_t x = c & ((1u << bx) - 1u);
+        return x == 0 ? 1u : (x == nx - 1 ? 2u : 0u);
+    }
     struct Raw {
         RowRaw own, ym, yp, zm, zp, mm, pp, mp, pm;
     };
@@ -391,6 +421,37 @@ __device__ __forceinline__ Mom collide_increment(const Mom& m, float jx, float j
     return h;
 }
 
+// ------------------------------------------------------------------ Zou-He
+// Pressure boundaries on the x faces (Sec. 2.2, 3.1).  On the plane x = 0
+// (side 1) the populations with c_x = +1, on x = nx - 1 (side 2) those with
+// c_x = -1, arrive from outside the image; they are rebuilt from the known
+// ones so that the node has the prescribed density deviation (drho_in /
+// drho_out), no transverse velocity, equal non-equilibrium parts of the
+// opposite pair along x, and diagonals that cancel the transverse momentum of
+// the in-plane populations.  f holds deviations (the w rho0 parts cancel).
+__device__ __forceinline__ void zou_he(float f[19], uint32_t side, float drho_in, float drho_out) {
+    const float H0 = f[0] + (f[3] + f[4]) + (f[5] + f[6]) + (f[15] + f[16]) + (f[17] + f[18]);
+    const float Ny = 0.5f * ((f[3] - f[4]) + (f[15] - f[16]) + (f[17] - f[18]));
+    const float Nz = 0.5f * ((f[5] - f[6]) + (f[15] - f[16]) - (f[17] - f[18]));
+    if (side == 1u) {
+        const float ju = drho_in - (H0 + 2.f * (f[2] + f[8] + f[10] + f[12] + f[14]));
+        const float j3 = ju * (1.f / 3.f), j6 = ju * (1.f / 6.f);
+        f[1] = f[2] + j3;
+        f[7] = f[8] + j6 - Ny;
+        f[9] = f[10] + j6 + Ny;
+        f[11] = f[12] + j6 - Nz;
+        f[13] = f[14] + j6 + Nz;
+    } else {
+        const float ju = (H0 + 2.f * (f[1] + f[7] + f[9] + f[11] + f[13])) - drho_out;
+        const float j3 = ju * (1.f / 3.f), j6 = ju * (1.f / 6.f);
+        f[2] = f[1] - j3;
+        f[8] = f[7] - j6 + Ny;
+        f[10] = f[9] - j6 - Ny;
+        f[12] = f[11] - j6 + Nz;
+        f[14] = f[13] - j6 - Nz;
+    }
+}
+
 // ------------------------------------------------------------------ TRT
 // Two-relaxation-time collision (Sec. 2.1.2) applied link-wise, for two-rate
 // sets (SRT, B, E): every even non-conserved moment relaxes at sp = s_nu and
@@ -510,13 +571,18 @@ __device__ __forceinline__ uint32_t wall_bits(const int32_t s[19]) {
 // in direction i the node reads slot opp(i) there and writes back the fh_opp(i)
 // the halfway gather brought (the previous step's); only the node itself
 // touches its slots.
-template <class C, class Ix, bool FIELD, bool TRT, bool FW>
+// ZH: Zou-He pressure boundaries on the x faces (bitmap index only, which
+// knows each node's x).
+template <class C, class Ix, bool FIELD, bool TRT, bool FW, bool ZH = false>
 __global__ void __launch_bounds__(kThreads)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
        uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
        const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
-       const double* __restrict__ prev_partials, double* __restrict__ prev_out, float* __restrict__ wall) {
+       const double* __restrict__ prev_partials, double* __restrict__ prev_out, float* __restrict__ wall,
+       float drho_in = 0.f, float drho_out = 0.f) {
     using T = typename C::T;
+    constexpr int S = C::kSlots;
+    constexpr bool REF = C::kRef;
     // The previous step's block partials are reduced here, by the first block,
     // so a time step is a single launch; kernel order makes them visible.
     if (prev_out != nullptr && blockIdx.x == 0) {
@@ -538,15 +604,17 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
         uint32_t n = node_of(c), n1 = node_of(c + G);
         typename Ix::Pre pre1 = ix.prefetch(n1);
         uint32_t off[19];
-        uint32_t wb = 0;  // wall links of node n (FW only)
+        uint32_t wb = 0;    // wall links of node n (FW only)
+        uint32_t side = 0;  // pressure face of node n (ZH only)
         {
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
             int32_t s[19];
             ix.sources(raw, p0, s);
-            gather_offsets<T>(s, n, c, slack, off);
-            if constexpr (FW) wb = wall_bits(s);
+            gather_offsets<T, S>(s, n, c, slack, off);
+            if constexpr (FW || REF) wb = wall_bits(s);
+            if constexpr (ZH) side = ix.x_face(p0);
         }
         for (;;) {
             // (1) index loads of the next node, (2) population loads of this
@@ -556,12 +624,25 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             typename Ix::Raw raw;
             ix.load(n1, pre1, raw);
             __builtin_amdgcn_sched_barrier(0);
-            const T* gb = chunk_base(src, c, slack);
+            const T* gb = chunk_base<T, S>(src, c, slack);
             T fr[19];
             unroll<19>([&](auto k) {
                 constexpr int i = decltype(k)::value;
                 fr[i] = ld_off(gb, off[i]);
             });
+            // REF: the reference density of the node each value came from (its
+            // last slot): the source node, or the node itself at a wall
+            T rr[19];
+            if constexpr (REF) {
+                unroll<19>([&](auto k) {
+                    constexpr int i = decltype(k)::value;
+                    constexpr uint32_t sz = sizeof(T);
+                    constexpr uint32_t adj_pull = (uint32_t)(S - 1 - i) * kThreads * sz;
+                    constexpr uint32_t adj_wall = (uint32_t)(S - 1 - opp(i)) * kThreads * sz;
+                    const uint32_t adj = ((wb >> i) & 1u) ? adj_wall : adj_pull;
+                    rr[i] = ld_off(gb, off[i] + adj);
+                });
+            }
             float wv[19];
             float* wc = FW ? wall + (size_t)c * kChunkElems : nullptr;
             const uint32_t own = (n & (kThreads - 1u)) * 4u;
@@ -573,18 +654,20 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             }
             const typename Ix::Pre pre2 = ix.prefetch(node_of(c + 2 * G));
             __builtin_amdgcn_sched_barrier(0);
-            const uint32_t wb_n = wb;
+            const uint32_t wb_n = wb, side_n = side;
             {
                 int32_t s[19];
                 ix.sources(raw, pre1, s);
-                gather_offsets<T>(s, n1, c + G, slack, off);
-                if constexpr (FW) wb = wall_bits(s);
+                gather_offsets<T, S>(s, n1, c + G, slack, off);
+                if constexpr (FW || REF) wb = wall_bits(s);
+                if constexpr (ZH) side = ix.x_face(pre1);
             }
             __builtin_amdgcn_sched_barrier(0);
             float f[19];
             unroll<19>([&](auto k) {
                 constexpr int i = decltype(k)::value;
                 f[i] = C::cvt(fr[i], inv);
+                if constexpr (REF) f[i] += wgt(i) * (float)rr[i];
             });
             if constexpr (FW) {
                 // wall link i: use the value of two steps ago, keep this one
@@ -599,6 +682,9 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
                     constexpr int i = decltype(k)::value + 1;
                     st_off(wc + opp(i) * kThreads, own, wv[i]);
                 });
+            }
+            if constexpr (ZH) {
+                if (side_n != 0u) zou_he(f, side_n, drho_in, drho_out);
             }
             float Fx = Fx0, Fy = Fy0, Fz = Fz0;
             if (FIELD) {
@@ -630,11 +716,24 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             acc[1] += live * (double)jy;
             acc[2] += live * (double)jz;
             acc[3] += live * (double)drho;
-            T* db = dst + (size_t)c * kChunkElems;
-            unroll<19>([&](auto k) {
-                constexpr int i = decltype(k)::value;
-                st_stream(db + i * kThreads, (n & (kThreads - 1u)) * (uint32_t)sizeof(T), C::enc(f[i], scale));
-            });
+            T* db = dst + (size_t)c * (S * kThreads);
+            const uint32_t so = (n & (kThreads - 1u)) * (uint32_t)sizeof(T);
+            if constexpr (REF) {
+                // the node's new reference: its density deviation, which the
+                // collision conserves, rounded to the stored type
+                const T r_new = (T)drho;
+                const float rf = (float)r_new;
+                st_stream(db + (S - 1) * kThreads, so, r_new);
+                unroll<19>([&](auto k) {
+                    constexpr int i = decltype(k)::value;
+                    st_stream(db + i * kThreads, so, C::enc(f[i] - wgt(i) * rf, scale));
+                });
+            } else {
+                unroll<19>([&](auto k) {
+                    constexpr int i = decltype(k)::value;
+                    st_stream(db + i * kThreads, so, C::enc(f[i], scale));
+                });
+            }
             c += G;
             if (c >= chunks) break;
             n = n1;
@@ -654,8 +753,12 @@ __global__ void k_zero(uint32_t* p, int64_t words) {
 template <class C>
 __global__ void k_rescale(typename C::T* p, int64_t count, float factor) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x)
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if constexpr (C::kRef) {
+            if ((i / kThreads) % C::kSlots == C::kSlots - 1) continue;  // reference slot: unscaled
+        }
         p[i] = C::enc(C::cvt(p[i], 1.f), factor);
+    }
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -860,9 +963,26 @@ hipError_t step_launch(const StepLaunch& a, Ix ix, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Zou-He pressure faces: FP32 storage, bitmap index, uniform (zero) force,
+// halfway bounce-back.
+template <bool TRT>
+hipError_t step_pressure(const StepLaunch& a, BitmapIdx ix, hipStream_t s) {
+    hipLaunchKernelGGL((k_step<CodecF32, BitmapIdx, false, TRT, false, true>), dim3(a.grid), dim3(kThreads), 0, s,
+                       static_cast<const float*>(a.src), static_cast<float*>(a.dst), ix, (uint32_t)a.idx.slack,
+                       (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr, a.scale, a.inv_scale, a.partials,
+                       a.prev_partials, a.prev_out, nullptr, a.drho_in, a.drho_out);
+    return hipGetLastError();
+}
+
 // Full-way bounce-back is built for FP32 storage only.
 template <class C, class Ix, bool TRT>
 hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
+    if (a.pressure) {
+        if constexpr (std::is_same<C, CodecF32>::value && std::is_same<Ix, BitmapIdx>::value) {
+            if (!a.wall && !a.field) return step_pressure<TRT>(a, ix, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if constexpr (std::is_same<C, CodecF32>::value) {
         if (a.wall) return step_launch<C, Ix, TRT, true>(a, ix, s);
     } else {
@@ -883,6 +1003,7 @@ hipError_t step_collision(const StepLaunch& a, hipStream_t s) {
         case kF32: return step_codec<CodecF32, TRT>(a, s);
         case kF16: return step_codec<CodecF16, TRT>(a, s);
         case kBF16: return step_codec<CodecBF16, TRT>(a, s);
+        case kF16R: return step_codec<CodecF16R, TRT>(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -915,10 +1036,12 @@ hipError_t step_occupancy(int storage, int index_kind, int collision, int* block
     if (index_kind == kTable) {                                         \
         if (storage == kF32) return LBM_OCC(CodecF32, TableIdx, R);     \
         if (storage == kF16) return LBM_OCC(CodecF16, TableIdx, R);     \
+        if (storage == kF16R) return LBM_OCC(CodecF16R, TableIdx, R);   \
         return LBM_OCC(CodecBF16, TableIdx, R);                         \
     }                                                                   \
     if (storage == kF32) return LBM_OCC(CodecF32, BitmapIdx, R);        \
     if (storage == kF16) return LBM_OCC(CodecF16, BitmapIdx, R);        \
+    if (storage == kF16R) return LBM_OCC(CodecF16R, BitmapIdx, R);      \
     return LBM_OCC(CodecBF16, BitmapIdx, R);
     if (collision == kTrt) {
         LBM_OCC2(true)
@@ -957,6 +1080,10 @@ hipError_t launch_rescale(int storage, void* p, int64_t count, float factor, hip
             break;
         case kBF16:
             hipLaunchKernelGGL(k_rescale<CodecBF16>, g, b, 0, s, static_cast<uint16_t*>(p), count,
+                               factor);
+            break;
+        case kF16R:
+            hipLaunchKernelGGL(k_rescale<CodecF16R>, g, b, 0, s, static_cast<_Float16*>(p), count,
                                factor);
             break;
         default: return hipErrorInvalidValue;

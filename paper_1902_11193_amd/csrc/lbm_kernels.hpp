@@ -8,7 +8,7 @@
 
 namespace lbm {
 
-enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2, kF16R = 3 };
 enum IndexKind : int { kTable = 0, kBitmap = 1 };
 enum Collision : int { kMrt = 0, kTrt = 1 };
 
@@ -44,6 +44,8 @@ struct StepLaunch {
     double* prev_out;             // ... into prev_out[0..3]; nullptr: nothing pending
     float* wall;          // full-way bounce-back: per-node fh of the previous step (state layout,
                           // FP32 storage only), or nullptr for halfway bounce-back
+    bool pressure;        // Zou-He pressure faces at x = 0 and x = nx - 1 (FP32, bitmap, no field)
+    float drho_in, drho_out;  // their density deviations rho - rho0
 };
 
 // One fused step: gather with halfway bounce-back, MRT + Guo collision, store,

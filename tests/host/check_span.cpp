@@ -25,24 +25,28 @@ int main() {
         std::vector<int32_t> t((size_t)18 * np, -1);
         build_table(g.data(), nx, ny, nz, nf, np, t.data());
         auto st = row_starts(g.data(), nx, ny, nz);
-        GatherSpan sp = gather_span(st, ny, nz);
-        const int64_t E = 19 * kChunk;
-        for (int64_t n = 0; n < nf; ++n) {
-            int64_t cb = (n / kChunk) * E;
-            auto check = [&](int64_t e) {
-                int64_t rel = e - cb + sp.slack;
-                if (rel < 0 || rel >= sp.slack + sp.reach || e < 0 || e >= 19 * np) {
-                    if (bad < 10) printf("BAD n=%lld e=%lld cb=%lld slack=%lld reach=%lld dims %d %d %d\n",
-                                         (long long)n, (long long)e, (long long)cb, (long long)sp.slack,
-                                         (long long)sp.reach, nx, ny, nz);
-                    ++bad;
+        for (int S : {19, 20}) {  // 19 populations, or 20 values with a reference-density slot
+            GatherSpan sp = gather_span(st, ny, nz, S);
+            const int64_t E = (int64_t)S * kChunk;
+            for (int64_t n = 0; n < nf; ++n) {
+                int64_t cb = (n / kChunk) * E;
+                auto check = [&](int64_t e) {
+                    int64_t rel = e - cb + sp.slack;
+                    if (rel < 0 || rel >= sp.slack + sp.reach || e < 0 || e >= S * np) {
+                        if (bad < 10) printf("BAD S=%d n=%lld e=%lld cb=%lld slack=%lld reach=%lld dims %d %d %d\n",
+                                             S, (long long)n, (long long)e, (long long)cb, (long long)sp.slack,
+                                             (long long)sp.reach, nx, ny, nz);
+                        ++bad;
+                    }
+                };
+                check(state_elem(0, n, S));
+                check(state_elem(S - 1, n, S));
+                for (int i = 1; i < 19; ++i) {
+                    int32_t s = t[(size_t)(i - 1) * np + n];
+                    check(s >= 0 ? state_elem(i, s, S) : state_elem(opposite(i), n, S));
+                    check(s >= 0 ? state_elem(S - 1, s, S) : state_elem(S - 1, n, S));
+                    check(state_elem(i, n, S));
                 }
-            };
-            check(state_elem(0, n));
-            for (int i = 1; i < 19; ++i) {
-                int32_t s = t[(size_t)(i - 1) * np + n];
-                check(s >= 0 ? state_elem(i, s) : state_elem(opposite(i), n));
-                check(state_elem(i, n));
             }
         }
         // node order is a permutation of the fluid voxels

@@ -140,7 +140,7 @@ def test_workspace_query_counts_and_errors():
     ptr = g.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     nbytes, n = ctypes.c_size_t(0), ctypes.c_int64(0)
     assert L.lbm_workspace_query(ptr, 0, 2, 2, 0, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
-    assert L.lbm_workspace_query(ptr, 2, 2, 2, 3, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
+    assert L.lbm_workspace_query(ptr, 2, 2, 2, 4, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
     assert L.lbm_workspace_query(ptr, 2, 2, 2, 0, 2, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
     assert L.lbm_workspace_query(None, 2, 2, 2, 0, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
 

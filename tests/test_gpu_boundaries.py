@@ -104,3 +104,66 @@ def test_wall_mode_errors():
     s.set_wall("halfway")
     s.step(2)
     s.close()
+
+
+@pytest.mark.parametrize("name,make", [("rand_x12", lambda: random_mask((6, 7, 12), 0.3, 31)),
+                                       ("slit", lambda: __import__("lbm_inputs").slit(10, 9, 3, 6))])
+@pytest.mark.parametrize("collision", ["mrt", "trt"])
+def test_pressure_faces_match_oracle(name, make, collision):
+    """Zou-He pressure inlet/outlet on the x faces against the oracle's."""
+    mask = make()
+    banner(f"pressure {name} {collision}")
+    rin, rout = 1 + 5e-5, 1 - 5e-5
+    s = P.Solver(mask, 0.9, 3 / 16, "E", (0.0, 0.0, 0.0), "f32", "bitmap")
+    s.set_collision(collision)
+    s.set_pressure(rin, rout)
+    f0 = random_state(s.n_fluid, 9, amp=1e-5)
+    s.set_state(f0)
+    f0 = s.get_state()
+    p = O.Problem(mask, 0.9, 3 / 16, "E", (0, 0, 0), collision=collision, pressure=(rin, rout))
+    fh = dense_from_lib(p, f0)
+    done = 0
+    for n in (1, 2, 50):
+        s.step(n - done)
+        for _ in range(n - done):
+            fh, u = p.step(fh)
+        done = n
+        err = deviation_error(s.get_state(), lib_from_dense(p, fh))
+        assert err < 2e-6, (name, n, err)
+        kg, ko = float(s.permeability()[0]), float(p.permeability(p.mean_velocity(u))[0])
+        assert abs(kg - ko) <= 1e-5 * abs(ko) + 1e-12, (n, kg, ko)
+    s.close()
+
+
+def test_pressure_driven_slit_permeability():
+    """At Lambda = 1/4 the pressure-driven slit reaches the closed form."""
+    from lbm_inputs import slit
+
+    banner("pressure slit k")
+    H, Ly = 8, 10
+    s = P.Solver(slit(12, Ly, 1, H), 0.8, 1 / 4, "E", (0.0, 0.0, 0.0), "f32", "bitmap")
+    s.set_pressure(1 + 5e-5, 1 - 5e-5)
+    r = s.run_to_steady(eps=1e-9, check_every=100, max_steps=20000)
+    k_exact = H * (H * H - 1 + 8 / 4) / (12 * Ly)
+    assert abs(float(r["k"][0]) / k_exact - 1) < 1e-4, (r, k_exact)
+    s.close()
+
+
+def test_pressure_mode_errors():
+    mask = random_mask((6, 6, 6), 0.3, 2)
+    banner("pressure errors")
+    for storage, index, g in (("f16", "bitmap", (0, 0, 0)), ("f32", "table", (0, 0, 0)),
+                              ("f32", "bitmap", (1e-6, 0, 0))):
+        s = P.Solver(mask, 0.9, 3 / 16, "E", g, storage, index)
+        with pytest.raises(P.LbmError) as e:
+            s.set_pressure(1.001, 0.999)
+        assert e.value.code == P.LBM_EINVAL
+        s.close()
+    s = P.Solver(mask, 0.9, 3 / 16, "E", (0, 0, 0), "f32", "bitmap")
+    with pytest.raises(P.LbmError):
+        s.set_pressure(1.0, 1.0)
+    s.set_pressure(1.001, 0.999)
+    with pytest.raises(P.LbmError):
+        s.adjoint(10, 5)
+    s.set_pressure(None)
+    s.close()

@@ -176,7 +176,7 @@ def test_run_to_steady_matches_oracle_step_count():
         assert abs(r["k"][0] / gold["k_final"] - 1) < 1e-6
 
 
-@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 1e-1)])
+@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 1e-1), ("f16r", 1e-3)])
 def test_reduced_storage_permeability(storage, tol):
     """k with FP16 / BF16 deviation storage against the FP64 oracle at equal N
     on a 32^3 crop of the porosity-0.2 Gaussian-random-field rock.  This crop
@@ -195,7 +195,7 @@ def test_reduced_storage_permeability(storage, tol):
     assert abs(k / ko - 1) < tol
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 3e-2), ("bf16", 5e-1)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 3e-2), ("bf16", 5e-1), ("f16r", 2e-3)])
 def test_grf_crop128_permeability_vs_oracle_golden(storage, tol):
     """128^3 crop of the 512^3 rock: k after 500, 1000, 2000 steps with each
     storage type against the FP64 oracle's values (tests/golden).  FP32 storage
