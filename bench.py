@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "MFLUPS & %HBM peak, D3Q19-MRT 512^3 pack: fp32 vs fp16-store vs adjoint"
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per fluid-lattice update: 19 populations read + 19 written.
-ALG_BYTES = {"f32": 19 * 4 * 2, "f16": 19 * 2 * 2, "bf16": 19 * 2 * 2}
+ALG_BYTES = {"f32": 19 * 4 * 2, "f16": 19 * 2 * 2, "bf16": 19 * 2 * 2, "f16r": 20 * 2 * 2}
 # Index bytes per node the design adds: int32 [18] table, or one packed coordinate.
 INDEX_BYTES = {"table": 18 * 4, "bitmap": 4}
 # Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n.
@@ -153,6 +153,35 @@ def cpu_baseline(mask_full, crop_n: int, steps: int):
                        f"({p.nf} fluid nodes), {t:.1f} s")
 
 
+def cpu_configs(steps: int):
+    """The FP64 oracle on each parity case (32^3 sphere array in full, 64^3
+    crop of the 256^3 pack, 128^3 crop of the 512^3 rock, 32^3 crop of the
+    128^3 pack), single-threaded and with all host threads."""
+    import torch
+
+    import oracle as O
+    from lbm_inputs import crop, workload
+
+    cases = [("sc_sphere_32", lambda: workload("sc_sphere_32")),
+             ("pack_256 crop 64", lambda: crop(workload("pack_256"), 64)),
+             ("grf_512 crop 128", lambda: crop(workload("grf_512"), 128)),
+             ("pack_128 crop 32", lambda: crop(workload("pack_128"), 32))]
+    nthreads = torch.get_num_threads()
+    out = []
+    for name, make in cases:
+        m = make()
+        p = O.Problem(m, 1.0, 3 / 16, "E", (1e-6, 0.0, 0.0))
+        row = dict(case=name, n_fluid=p.nf, steps=steps)
+        for th in (1, nthreads):
+            torch.set_num_threads(th)
+            t = O.time_steps(p, steps)
+            row[f"MFLUPS_{th}_threads"] = p.nf * steps / t / 1e6
+        torch.set_num_threads(nthreads)
+        print(f"[bench] oracle {name}: {row}", file=sys.stderr, flush=True)
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,7 +189,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grf_512")
     ap.add_argument("--index", default="bitmap", choices=["bitmap", "table"])
-    ap.add_argument("--variants", default="f16,bf16,trt,f16_trt,adjoint")
+    ap.add_argument("--variants", default="f16,bf16,f16r,trt,f16_trt,adjoint")
     ap.add_argument("--tau", type=float, default=1.0)
     ap.add_argument("--Lambda", type=float, default=3 / 16)
     ap.add_argument("--g", type=float, default=None)
@@ -169,11 +198,14 @@ def main():
     ap.add_argument("--cpu-crop", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-configs", type=int, default=0, metavar="STEPS",
+                    help="also time the oracle on every parity case for STEPS steps (1 thread and all)")
     ap.add_argument("--steady", action="store_true",
                     help="also run FP32 and FP16 storage to steady state and compare k")
     ap.add_argument("--eps", type=float, default=1e-6)
     ap.add_argument("--max-steps", type=int, default=30000)
     ap.add_argument("--steady-extra", type=int, default=3000)
+    ap.add_argument("--steady-storages", default="f32,f16,f16r")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device (a kernel of known traffic for counter calibration)")
     args = ap.parse_args()
@@ -209,7 +241,7 @@ def main():
     print(f"[bench] f32 {main_r['MFLUPS']:.0f} MFLUPS {main_r['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     variants = {}
     for v in [x for x in args.variants.split(",") if x]:
-        if v in ("f16", "bf16"):
+        if v in ("f16", "bf16", "f16r"):
             variants[f"{v}_store"] = run_forward(P, mask, args, v)
             variants[f"{v}_store"]["k_rel_vs_f32"] = variants[f"{v}_store"]["k_after_timed"] / main_r["k_after_timed"] - 1
         elif v in ("trt", "f16_trt"):
@@ -224,9 +256,12 @@ def main():
 
     steady = None
     if args.steady:
-        steady = {st: run_steady(P, mask, args, st) for st in ("f32", "f16")}
-        steady["k_rel_f16_vs_f32"] = steady["f16"]["k"] / steady["f32"]["k"] - 1
-        steady["k_rel_f16_vs_f32_after_extra"] = steady["f16"]["k_after_extra"] / steady["f32"]["k_after_extra"] - 1
+        steady = {st: run_steady(P, mask, args, st) for st in args.steady_storages.split(",")}
+        for st in [x for x in steady if x != "f32"]:
+            if "f32" in steady:
+                steady[f"k_rel_{st}_vs_f32"] = steady[st]["k"] / steady["f32"]["k"] - 1
+                steady[f"k_rel_{st}_vs_f32_after_extra"] = (steady[st]["k_after_extra"] /
+                                                           steady["f32"]["k_after_extra"] - 1)
 
     nf = int((mask == 0).sum())
     alg_per_launch = ALG_BYTES["f32"] * nf
@@ -261,6 +296,8 @@ def main():
     }
     if steady is not None:
         out["steady"] = steady
+    if args.cpu_configs:
+        out["cpu_configs"] = cpu_configs(args.cpu_configs)
     print(json.dumps(out))
 
 

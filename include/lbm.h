@@ -161,6 +161,13 @@ int lbm_boundary_dims(int nx, int ny, int nz, int pad, int mirror_y, int mirror_
 int lbm_boundary_image(const uint8_t* geometry, int nx, int ny, int nz, int pad, int mirror_y, int mirror_z,
                        uint8_t* out);
 
+/* Host only (no GPU needed).  Pull sources of selected nodes, as in
+ * lbm_neighbor_table but for nodes[count] only (node numbers in node order):
+ * table[18][count] int32, entry (i-1)*count + k, -1 where the source voxel is
+ * solid.  Caller-owned host arrays.  LBM_EINVAL for a node out of range. */
+int lbm_neighbor_nodes(const uint8_t* geometry, int nx, int ny, int nz, const int64_t* nodes, int64_t count,
+                       int32_t* table);
+
 /* Host only (no GPU needed).  Linear voxel id x + nx (y + ny z) of every
  * node, in node order: voxel[n_fluid] int64, owned by the caller. */
 int lbm_node_order(const uint8_t* geometry, int nx, int ny, int nz, int64_t* voxel,
@@ -215,6 +222,11 @@ int lbm_history(lbm_ctx* ctx, int count, double* u);
  * entries converges in that case. */
 int lbm_run_to_steady(lbm_ctx* ctx, double eps, int check_every, int max_steps, int* steps,
                       double k[3], int* converged);
+
+/* Host.  The state of selected nodes only (full populations f_i, FP64,
+ * f[19][count], entry i*count + k), read chunk by chunk from the device:
+ * for sampled checks of images too large to copy whole.  Synchronises. */
+int lbm_get_state_nodes(lbm_ctx* ctx, const int64_t* nodes, int64_t count, double* f);
 
 /* Host copies of the state: full populations f_i = w_i rho0 + deviation in
  * FP64, layout [19][n_fluid] (host memory owned by the caller).

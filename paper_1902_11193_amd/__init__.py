@@ -53,6 +53,8 @@ SIGNATURES = {
     "lbm_wall_workspace_query": (c_int, [c_void_p, c_void_p]),
     "lbm_set_wall": (c_int, [c_void_p, c_int, c_void_p, c_size_t]),
     "lbm_set_pressure": (c_int, [c_void_p, c_int, c_double, c_double]),
+    "lbm_neighbor_nodes": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int64, c_void_p]),
+    "lbm_get_state_nodes": (c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
     "lbm_boundary_dims": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "lbm_boundary_image": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p]),
     "lbm_adjoint_workspace_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
@@ -141,6 +143,16 @@ def lbm_node_order(geometry) -> np.ndarray:
     v = np.empty(max(nf, 1), np.int64)
     _check(lib().lbm_node_order(_dptr(g, c_uint8), nx, ny, nz, _dptr(v, c_int64), nf))
     return v[:nf]
+
+
+def lbm_neighbor_nodes(geometry, nodes) -> np.ndarray:
+    """Pull sources (18, len(nodes)) of the given nodes (-1: solid source)."""
+    g, nx, ny, nz = _geom(geometry)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+    t = np.empty((18, max(len(nodes), 1)), np.int32)
+    _check(lib().lbm_neighbor_nodes(_dptr(g, c_uint8), nx, ny, nz, _dptr(nodes, c_int64), len(nodes),
+                                    _dptr(t, c_int32)))
+    return t[:, :len(nodes)]
 
 
 def lbm_boundary_image(geometry, pad: int = 5, mirror_y: bool = True, mirror_z: bool = True) -> np.ndarray:
@@ -234,6 +246,13 @@ class Solver:
         f = np.zeros((19, self.n_fluid))
         _check(lib().lbm_get_state(self._ctx, _dptr(f, c_double)))
         return f
+
+    def get_state_nodes(self, nodes) -> np.ndarray:
+        """Full populations (19, len(nodes)) of the given nodes only."""
+        nodes = np.ascontiguousarray(nodes, dtype=np.int64)
+        f = np.zeros((19, max(len(nodes), 1)))
+        _check(lib().lbm_get_state_nodes(self._ctx, _dptr(nodes, c_int64), len(nodes), _dptr(f, c_double)))
+        return f[:, :len(nodes)]
 
     def set_state(self, f: np.ndarray):
         f = np.ascontiguousarray(f, dtype=np.float64)
@@ -351,4 +370,4 @@ def permeability(geometry, tau, Lambda, g_field, relaxation_set="E", g_ref=(1e-6
 
 
 __all__ = ["lib", "LbmError", "Solver", "permeability", "lbm_velocities", "lbm_rates", "lbm_workspace_query",
-           "lbm_neighbor_table", "lbm_node_order", "lbm_boundary_image", "raster_permutation", "SIGNATURES", "SETS", "STORAGE", "INDEX", "COLLISION", "WALL", "LIB_PATH"]
+           "lbm_neighbor_table", "lbm_neighbor_nodes", "lbm_node_order", "lbm_boundary_image", "raster_permutation", "SIGNATURES", "SETS", "STORAGE", "INDEX", "COLLISION", "WALL", "LIB_PATH"]

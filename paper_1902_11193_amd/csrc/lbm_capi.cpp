@@ -292,6 +292,18 @@ int lbm_neighbor_table(const uint8_t* geometry, int nx, int ny, int nz, int32_t*
     return LBM_OK;
 }
 
+int lbm_neighbor_nodes(const uint8_t* geometry, int nx, int ny, int nz, const int64_t* nodes, int64_t count,
+                       int32_t* table) {
+    std::string e = check_common(geometry, nx, ny, nz, LBM_F32, LBM_INDEX_TABLE);
+    if (!e.empty()) return fail(LBM_EINVAL, e);
+    if (count < 0 || (count > 0 && (!nodes || !table))) return fail(LBM_EINVAL, "NULL argument or count < 0");
+    const int64_t nf = lbm::count_fluid(geometry, nx, ny, nz);
+    for (int64_t k = 0; k < count; ++k)
+        if (nodes[k] < 0 || nodes[k] >= nf) return fail(LBM_EINVAL, "node number out of range");
+    lbm::neighbor_nodes(geometry, nx, ny, nz, nodes, count, table);
+    return LBM_OK;
+}
+
 int lbm_node_order(const uint8_t* geometry, int nx, int ny, int nz, int64_t* voxel,
                    int64_t n_fluid) {
     std::string e = check_common(geometry, nx, ny, nz, LBM_F32, LBM_INDEX_TABLE);
@@ -571,6 +583,44 @@ int lbm_get_state(lbm_ctx* c, double* f) {
             else
                 d = (double)from_bf16(reinterpret_cast<const uint16_t*>(raw.data())[at]);
             f[(size_t)i * c->nf + n] = w + d;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_get_state_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double* f) {
+    if (!c || (count > 0 && (!nodes || !f)) || count < 0) return fail(LBM_EINVAL, "NULL argument or count < 0");
+    for (int64_t k = 0; k < count; ++k)
+        if (nodes[k] < 0 || nodes[k] >= c->nf) return fail(LBM_EINVAL, "node number out of range");
+    const size_t es = elem_size(c->storage);
+    const int S = slots(c->storage);
+    const size_t chunk_bytes = (size_t)S * lbm::kChunk * es;
+    std::vector<char> buf(chunk_bytes);
+    const double inv = 1.0 / std::ldexp(1.0, c->exponent);
+    int64_t loaded = -1;
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t n = nodes[k], q = n / lbm::kChunk;
+        if (q != loaded) {  // the node's chunk holds all its values
+            HIP_TRY(hipMemcpyAsync(buf.data(), static_cast<char*>(c->cur) + (size_t)q * chunk_bytes, chunk_bytes,
+                                   hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));
+            loaded = q;
+        }
+        const int64_t m = n % lbm::kChunk;
+        const _Float16* h16 = reinterpret_cast<const _Float16*>(buf.data());
+        for (int i = 0; i < 19; ++i) {
+            const size_t at = (size_t)lbm::state_elem(i, m, S);
+            double d;
+            if (c->storage == LBM_F32)
+                d = reinterpret_cast<const float*>(buf.data())[at];
+            else if (c->storage == LBM_F16)
+                d = (double)(float)h16[at] * inv;
+            else if (c->storage == LBM_F16R)
+                d = (double)((float)h16[at] * (float)inv +
+                             (float)weight(i) * (float)h16[lbm::state_elem(S - 1, m, S)]);
+            else
+                d = (double)from_bf16(reinterpret_cast<const uint16_t*>(buf.data())[at]);
+            f[(size_t)i * count + k] = weight(i) + d;
         }
     }
     return LBM_OK;

@@ -297,6 +297,51 @@ void boundary_image(const uint8_t* g, int nx, int ny, int nz, int pad, bool mirr
     });
 }
 
+void neighbor_nodes(const uint8_t* g, int nx, int ny, int nz, const int64_t* nodes, int64_t count,
+                    int32_t* out) {
+    const auto start = row_starts(g, nx, ny, nz);
+    const int64_t rows = (int64_t)ny * nz;
+    // rows holding fluid, sorted by their first node number (distinct starts)
+    std::vector<int64_t> order;
+    for (int64_t r = 0; r < rows; ++r) {
+        const uint8_t* p = g + r * nx;
+        for (int x = 0; x < nx; ++x)
+            if (p[x] == 0) {
+                order.push_back(r);
+                break;
+            }
+    }
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return start[a] < start[b]; });
+    auto node_at = [&](int x, int y, int z) -> int32_t {  // node number of a voxel, -1 if solid
+        const int64_t r = (int64_t)z * ny + y;
+        const uint8_t* p = g + r * nx;
+        if (p[x] != 0) return -1;
+        int64_t k = 0;
+        for (int q = 0; q < x; ++q) k += (p[q] == 0);
+        return (int32_t)(start[r] + k);
+    };
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t n = nodes[k];
+        // the fluid row with the largest first node <= n holds node n
+        const auto it = std::upper_bound(order.begin(), order.end(), n,
+                                         [&](int64_t v, int64_t r) { return v < start[r]; });
+        const int64_t r = *(it - 1);
+        const int z = (int)(r / ny), y = (int)(r % ny);
+        int64_t want = n - start[r];
+        const uint8_t* p = g + r * nx;
+        int x = 0;
+        for (;; ++x)
+            if (p[x] == 0 && want-- == 0) break;
+        for (int i = 1; i < 19; ++i) {
+            int sx = x - kC[i][0], sy = y - kC[i][1], sz = z - kC[i][2];
+            sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+            sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+            sz = sz < 0 ? sz + nz : (sz >= nz ? sz - nz : sz);
+            out[(int64_t)(i - 1) * count + k] = node_at(sx, sy, sz);
+        }
+    }
+}
+
 void fluid_voxels(const uint8_t* g, int nx, int ny, int nz, int64_t* out) {
     auto start = row_starts(g, nx, ny, nz);
     parallel_slabs(nz, (int64_t)nx * ny * nz, [&](int z0, int z1) {

@@ -109,6 +109,11 @@ void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, Bitma
 void boundary_image(const uint8_t* geom, int nx, int ny, int nz, int pad, bool mirror_y, bool mirror_z,
                     uint8_t* out);
 
+// Pull sources [18][count] (entry (i-1)*count + k; -1 = solid source) of the
+// given nodes only, found from the row starts without the full table.
+void neighbor_nodes(const uint8_t* geom, int nx, int ny, int nz, const int64_t* nodes, int64_t count,
+                    int32_t* out);
+
 // Linear voxel id x + nx (y + ny z) of every fluid node, in node order.
 void fluid_voxels(const uint8_t* geom, int nx, int ny, int nz, int64_t* out);
 

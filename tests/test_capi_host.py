@@ -213,3 +213,14 @@ def test_boundary_image_rejects_bad_arguments():
     with pytest.raises(P.LbmError) as e:
         P.lbm_boundary_image(m, -1)
     assert e.value.code == P.LBM_EINVAL
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (40, 3, 9), (3, 2, 130)])
+def test_neighbor_nodes_equal_the_full_table(shape):
+    m = random_mask(shape, 0.3, 4)
+    t = P.lbm_neighbor_table(m)
+    rng = np.random.default_rng(1)
+    pick = rng.choice(t.shape[1], min(50, t.shape[1]), replace=False)
+    assert np.array_equal(P.lbm_neighbor_nodes(m, pick), t[:, pick])
+    with pytest.raises(P.LbmError):
+        P.lbm_neighbor_nodes(m, np.array([t.shape[1]]))

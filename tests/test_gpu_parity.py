@@ -296,3 +296,23 @@ def test_sampled_full_size_step_grf_512():
     assert deviation_error(got, want) < 2e-6
     assert abs(s.mass_deviation()) < 1e-3 * nf * 1e-6
     del c
+
+
+def test_pack256_crop64_matches_oracle():
+    """The 256^3 sphere pack's 64^3 corner crop (re-filtered for x-spanning
+    fluid): k after 50 and 200 steps from rest against the FP64 oracle, for
+    Set E at the ends of the pack study's relaxation times."""
+    m = crop(workload("pack_256"), 64)
+    for tau in (0.6, 1.3):
+        banner(f"pack256 crop64 tau={tau}")
+        p = oracle_problem(m, tau, 3 / 16, "E", (1e-6, 0, 0))
+        r = O.run(p, 200, keep_state=False)
+        s = P.Solver(m, tau, 3 / 16, "E", (1e-6, 0, 0))
+        s.step(50)
+        k50 = s.permeability()[0]
+        s.step(150)
+        k200 = s.permeability()[0]
+        ko50 = float(p.permeability(r["umean"][49])[0])
+        ko200 = float(r["k"][0])
+        assert abs(k50 / ko50 - 1) < 1e-6 and abs(k200 / ko200 - 1) < 1e-6, (tau, k50, ko50, k200, ko200)
+        s.close()
