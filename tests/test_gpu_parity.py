@@ -176,12 +176,14 @@ def test_run_to_steady_matches_oracle_step_count():
         assert abs(r["k"][0] / gold["k_final"] - 1) < 1e-6
 
 
-@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 1e-1), ("f16r", 1e-3)])
+@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 1e-1), ("f16r", 2e-4)])
 def test_reduced_storage_permeability(storage, tol):
     """k with FP16 / BF16 deviation storage against the FP64 oracle at equal N
     on a 32^3 crop of the porosity-0.2 Gaussian-random-field rock.  This crop
     is nearly blocked (k ~ 2e-3): density deviations exceed the velocity by
-    ~1e3, so the 8-bit BF16 mantissa resolves the flow only to ~1e-1."""
+    ~1e3, so the 8-bit BF16 mantissa resolves the flow only to ~1e-1.  FP16
+    with the per-node reference density rounds only the velocity-sized part
+    (measured 3.6e-5)."""
     rock = gaussian_random_field(64, 6.0, 0.2, seed=1904)
     m = crop(rock, 32)
     banner(f"reduced storage {storage} grf crop 32")
@@ -195,14 +197,16 @@ def test_reduced_storage_permeability(storage, tol):
     assert abs(k / ko - 1) < tol
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 3e-2), ("bf16", 5e-1), ("f16r", 2e-3)])
+@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 3e-2), ("bf16", 5e-1), ("f16r", 3e-5)])
 def test_grf_crop128_permeability_vs_oracle_golden(storage, tol):
     """128^3 crop of the 512^3 rock: k after 500, 1000, 2000 steps with each
     storage type against the FP64 oracle's values (tests/golden).  FP32 storage
     meets 1e-6.  The crop is poorly connected (k ~ 2e-2) and pressure builds up
     in its dead ends: density deviations grow to ~1e3 times the flow signal,
     so FP16 storage (11-bit mantissa) drifts from ~1e-3 at 500-1000 steps to
-    ~1.5e-2 at 2000 steps; the bounds here are that measured envelope."""
+    ~1.5e-2 at 2000 steps; the bounds here are that measured envelope.  FP16
+    relative to the per-node reference density keeps the density part out of
+    the FP16 rounding and stays within 5e-6 (3e-5 allowed)."""
     path = os.path.join(os.path.dirname(__file__), "golden", "grf_crop128.json")
     if not os.path.exists(path):
         pytest.skip("grf_crop128.json not generated")
