@@ -89,3 +89,34 @@ def test_autograd_function_matches_solver_adjoint():
     assert abs(lam.grad.item() - ref["dk_dLambda"]) <= 1e-5 * max(abs(ref["dk_dLambda"]), ref["k"])
     scale = ref["dk_dg"].abs().max().item()
     assert (gfield.grad.double() - ref["dk_dg"]).abs().max().item() < 1e-5 * scale
+
+
+@pytest.mark.parametrize("rset,Lam", [("SRT", None), ("E", 3 / 16)])
+def test_adjoint_full_size_pack_128_vs_finite_differences(rset, Lam):
+    """128^3 pack, 4000 steps: dk/dtau and dk/dLambda of the adjoint against
+    central differences of the GPU forward itself (FP32 storage, so the step
+    is h = 1e-3 relative and the bound 1e-3 of the scale k/tau, the FP32 noise
+    of a difference of two k over 2h).  SRT has a large dk/dtau; Set E's is
+    ~0 by design and its dk/dLambda is large."""
+    m = workload("pack_128")
+    tau, g, N = 1.0, (1e-6, 0, 0), 4000
+    banner(f"adjoint vs FD pack_128 {rset}")
+    s = P.Solver(m, tau, Lam, rset, g)
+    r = s.adjoint(N, 200)
+    s.close()
+
+    def k_at(t, lam):
+        q = P.Solver(m, t, lam, rset, g)
+        q.step(N)
+        k = float(q.permeability()[0])
+        q.close()
+        return k
+
+    h = 1e-3 * tau
+    fd_tau = (k_at(tau + h, Lam) - k_at(tau - h, Lam)) / (2 * h)
+    scale = r["k"] / tau
+    assert abs(r["dk_dtau"] - fd_tau) < 1e-3 * max(abs(fd_tau), scale), (r["dk_dtau"], fd_tau)
+    if rset == "E":
+        hl = 1e-3 * Lam
+        fd_lam = (k_at(tau, Lam + hl) - k_at(tau, Lam - hl)) / (2 * hl)
+        assert abs(r["dk_dLambda"] - fd_lam) < 1e-3 * max(abs(fd_lam), r["k"]), (r["dk_dLambda"], fd_lam)

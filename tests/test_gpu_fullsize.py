@@ -31,7 +31,7 @@ def _oracle_step(f_src, sample, t, fo_of):
     for i in range(1, 19):
         j = i + 1 if i % 2 else i - 1
         src = t[i - 1]
-        pulled = fo_of(np.maximum(src, 0))[i]
+        pulled = fo_of(np.where(src >= 0, src, sample))[i]   # wall entries are not used
         own = fo_of(sample)[j]
         f[i] = np.where(src >= 0, pulled, own)
     lat = O.Lattice.make()
