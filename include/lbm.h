@@ -258,7 +258,7 @@ int lbm_set_collision(lbm_ctx* ctx, int collision);
  * the mode): it holds every node's populations of one step earlier, and is
  * initialised to the current state (as is again by lbm_set_state).
  * LBM_WALL_HALFWAY releases it (workspace may be NULL).  Errors: LBM_EINVAL
- * (unknown mode, FP16/BF16 storage), LBM_EWORKSPACE.  lbm_adjoint refuses a
+ * (unknown mode, storage other than FP32), LBM_EWORKSPACE.  lbm_adjoint refuses a
  * context in full-way mode. */
 int lbm_wall_workspace_query(lbm_ctx* ctx, size_t* bytes);
 int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes);
