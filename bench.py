@@ -83,7 +83,9 @@ def run_forward(P, mask, args, storage, collision="mrt"):
     mflups = nf / (ms * 1e-3) / 1e6
     alg_gbs = ALG_BYTES[storage] * nf / (ms * 1e-3) / 1e9
     des_gbs = (ALG_BYTES[storage] + INDEX_BYTES[args.index]) * nf / (ms * 1e-3) / 1e9
-    return dict(ms_per_step=ms, MFLUPS=mflups, GBps_algorithmic=alg_gbs, GBps_designed=des_gbs,
+    voxel_mlups = mask.size / (ms * 1e-3) / 1e6   # per voxel of the image, as dense codes count
+    return dict(ms_per_step=ms, MFLUPS=mflups, MLUPS_per_voxel=voxel_mlups, GBps_algorithmic=alg_gbs,
+                GBps_designed=des_gbs,
                 frac_hbm_algorithmic=alg_gbs / HBM_PEAK_GBS, k_after_timed=k,
                 steps_total=args.warmup + args.steps, wall_s=wall)
 
