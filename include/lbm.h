@@ -277,6 +277,15 @@ int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes
  * lbm_adjoint refuses a context with pressure faces. */
 int lbm_set_pressure(lbm_ctx* ctx, int enable, double rho_in, double rho_out);
 
+/* Host only.  With enable != 0 (the default), lbm_step and
+ * lbm_run_to_steady run stretches of 32 steps, once a step is pending, by
+ * replaying a HIP graph captured from the same launches on first use (one
+ * launch call per 32 steps: small images are otherwise launch-bound).  The
+ * results are identical to plain launches, which enable = 0 selects.  Any
+ * change of collision, wall, pressure, force field or storage exponent drops
+ * the captured graphs. */
+int lbm_set_graphs(lbm_ctx* ctx, int enable);
+
 /* FP16 storage keeps 2^e (f_i - w_i rho0); e defaults to
  * round(-log2 max|g|) - 4, and for LBM_F16R to round(-log2 max|g|) + 2
  * (its values are velocity-sized).  May be changed at any time (the state is

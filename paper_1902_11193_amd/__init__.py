@@ -55,6 +55,7 @@ SIGNATURES = {
     "lbm_set_pressure": (c_int, [c_void_p, c_int, c_double, c_double]),
     "lbm_neighbor_nodes": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int64, c_void_p]),
     "lbm_get_state_nodes": (c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "lbm_set_graphs": (c_int, [c_void_p, c_int]),
     "lbm_boundary_dims": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "lbm_boundary_image": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p]),
     "lbm_adjoint_workspace_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
@@ -279,6 +280,10 @@ class Solver:
 
     def set_storage_exponent(self, e: int):
         _check(lib().lbm_set_storage_exponent(self._ctx, int(e)))
+
+    def set_graphs(self, enable: bool):
+        """Replay captured 32-step graphs (default) or launch every step."""
+        _check(lib().lbm_set_graphs(self._ctx, int(bool(enable))))
 
     def set_collision(self, kind: str):
         """'mrt' (moment space, any set) or 'trt' (link-wise, SRT / B / E)."""

@@ -29,7 +29,8 @@ int fail(int code, const std::string& msg) {
             return fail(LBM_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));   \
     } while (0)
 
-constexpr int kRing = 1024;
+constexpr int kRing = (int)lbm::kRingSlots;
+constexpr int kGraphSteps = 32;  // steps per captured graph (even: the buffers return to place)
 constexpr int kMaxGrid = 8192;
 constexpr double kW[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
 
@@ -70,8 +71,8 @@ Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int n
     }
     L.partials = off;  // two buffers: steps alternate between them
     off += 2 * align256((size_t)kMaxGrid * 4 * 8);
-    L.ring = off;
-    off += align256((size_t)kRing * 4 * 8);
+    L.ring = off;  // ring of per-step sums, then the device counter of steps reduced
+    off += align256((size_t)kRing * 4 * 8 + sizeof(uint32_t));
     L.total = off;
     return L;
 }
@@ -138,11 +139,22 @@ struct lbm_ctx {
     int grid;
     double* partials[2];
     double* ring;
+    uint32_t* ctr;      // steps reduced into the ring so far (device, after the ring)
     int64_t steps;
     bool pending;  // the last step's partials are not yet reduced into the ring
     const float* field;
     int exponent;
     std::vector<uint8_t> geom;
+    // captured kGraphSteps-step sequences, by (cur buffer, step parity); any
+    // change of what a step launch bakes in drops them
+    bool graphs;
+    hipStream_t cap_stream;
+    hipGraphExec_t gexec[4];
+    ~lbm_ctx() {
+        for (auto& g : gexec)
+            if (g) hipGraphExecDestroy(g);
+        if (cap_stream) hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace {
@@ -155,9 +167,10 @@ lbm::RatesF rates_f(const lbm::RateClasses& r) {
 float scale_of(const lbm_ctx* c) { return std::ldexp(1.0f, c->exponent); }
 
 // One forward step from `src` to `dst` with partial sums into `partials`;
-// when prev_out is non-null the same launch reduces prev_partials into it.
+// when prev_partials is non-null the same launch reduces them into the next
+// ring slot (the device counter's).
 hipError_t step_raw(lbm_ctx* c, const void* src, void* dst, double* partials,
-                    const double* prev_partials = nullptr, double* prev_out = nullptr) {
+                    const double* prev_partials = nullptr, hipStream_t stream = nullptr) {
     lbm::StepLaunch a{};
     a.storage = c->storage;
     a.collision = c->collision;
@@ -179,8 +192,53 @@ hipError_t step_raw(lbm_ctx* c, const void* src, void* dst, double* partials,
     a.grid = c->grid;
     a.partials = partials;
     a.prev_partials = prev_partials;
-    a.prev_out = prev_out;
-    return lbm::launch_step(a, c->stream);
+    a.ring = c->ring;
+    a.ctr = c->ctr;
+    return lbm::launch_step(a, stream ? stream : c->stream);
+}
+
+void drop_graphs(lbm_ctx* c) {
+    for (auto& g : c->gexec)
+        if (g) {
+            hipGraphExecDestroy(g);
+            g = nullptr;
+        }
+}
+
+hipError_t zero_ring(lbm_ctx* c) {
+    return lbm::launch_zero(c->ring, (int64_t)kRing * 4 * 8 + (int64_t)sizeof(uint32_t), c->stream);
+}
+
+// The graph of kGraphSteps steps from the current buffers and step parity,
+// with the previous step's partials pending (captured on first use).
+hipGraphExec_t graph_for(lbm_ctx* c) {
+    const int key = (c->cur == c->ws + c->L.A ? 0 : 2) + (int)(c->steps & 1);
+    if (c->gexec[key]) return c->gexec[key];
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return nullptr;
+    }
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+    void* cur = c->cur;
+    void* nxt = c->nxt;
+    hipError_t he = hipSuccess;
+    for (int k = 0; k < kGraphSteps && he == hipSuccess; ++k) {
+        const int64_t t = c->steps + k;
+        he = step_raw(c, cur, nxt, c->partials[t & 1], c->partials[(t - 1) & 1], c->cap_stream);
+        std::swap(cur, nxt);
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t he2 = hipStreamEndCapture(c->cap_stream, &graph);
+    if (he != hipSuccess || he2 != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        return nullptr;
+    }
+    hipGraphExec_t exec = nullptr;
+    he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (he != hipSuccess) return nullptr;
+    c->gexec[key] = exec;
+    return exec;
 }
 
 // One resident wave of blocks: every block starts at once and walks the
@@ -202,19 +260,30 @@ bool two_rate(const lbm::RateClasses& r) {
     return r.s_e == r.s_nu && r.s_eps == r.s_nu && r.s_pi == r.s_nu && r.s_m == r.s_q;
 }
 
-double* slot(lbm_ctx* c, int64_t step_index) { return c->ring + (step_index % kRing) * 4; }
-
 // Step n (0-based) writes partials[n % 2]; its launch also reduces the
-// partials of step n-1 into the ring.
+// partials of step n-1 into the ring.  With a step pending, runs of
+// kGraphSteps steps replay a captured graph (one launch call instead of
+// kGraphSteps; the launches and their arguments are the same).
 int do_steps(lbm_ctx* c, int n) {
-    for (int k = 0; k < n; ++k) {
+    int k = 0;
+    while (k < n) {
+        if (c->graphs && c->pending && n - k >= kGraphSteps) {
+            hipGraphExec_t g = graph_for(c);
+            if (g) {
+                HIP_TRY(hipGraphLaunch(g, c->stream));
+                c->steps += kGraphSteps;  // even: cur and nxt are back in place
+                k += kGraphSteps;
+                continue;
+            }
+            c->graphs = false;  // capture not available: plain launches from here on
+        }
         const int64_t t = c->steps;
         const double* prev = c->pending ? c->partials[(t - 1) & 1] : nullptr;
-        double* prev_out = c->pending ? slot(c, t - 1) : nullptr;
-        HIP_TRY(step_raw(c, c->cur, c->nxt, c->partials[t & 1], prev, prev_out));
+        HIP_TRY(step_raw(c, c->cur, c->nxt, c->partials[t & 1], prev));
         std::swap(c->cur, c->nxt);
         ++c->steps;
         c->pending = true;
+        ++k;
     }
     return LBM_OK;
 }
@@ -222,8 +291,7 @@ int do_steps(lbm_ctx* c, int n) {
 // Reduce the last step's partials if that has not happened yet.
 int flush(lbm_ctx* c) {
     if (!c->pending) return LBM_OK;
-    HIP_TRY(lbm::launch_finalize(c->partials[(c->steps - 1) & 1], c->grid, slot(c, c->steps - 1),
-                                 c->stream));
+    HIP_TRY(lbm::launch_finalize(c->partials[(c->steps - 1) & 1], c->grid, c->ring, c->ctr, c->stream));
     c->pending = false;
     return LBM_OK;
 }
@@ -393,6 +461,10 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     c->partials[1] = c->partials[0] + align256((size_t)kMaxGrid * 4 * 8) / 8;
     c->pending = false;
     c->ring = reinterpret_cast<double*>(c->ws + c->L.ring);
+    c->ctr = reinterpret_cast<uint32_t*>(c->ring + (size_t)kRing * 4);
+    c->graphs = true;
+    c->cap_stream = nullptr;
+    for (auto& g : c->gexec) g = nullptr;
     c->steps = 0;
     c->field = nullptr;
     c->geom.assign(geometry, geometry + (size_t)nx * ny * nz);
@@ -451,7 +523,7 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
                                 hipMemcpyHostToDevice, c->stream);
     }
     if (he == hipSuccess) he = lbm::launch_zero(c->ws + c->L.A, (int64_t)(c->L.B - c->L.A) * 2, c->stream);
-    if (he == hipSuccess) he = lbm::launch_zero(c->ws + c->L.ring, (int64_t)kRing * 4 * 8, c->stream);
+    if (he == hipSuccess) he = zero_ring(c);
     if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
     if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("setup upload: ") + hipGetErrorString(he)));
     *ctx = c;
@@ -662,7 +734,7 @@ int lbm_set_state(lbm_ctx* c, const double* f) {
     HIP_TRY(hipMemcpyAsync(c->cur, raw.data(), raw.size(), hipMemcpyHostToDevice, c->stream));
     if (c->wall_mode == LBM_WALL_FULLWAY)  // the state one step older starts equal to it
         HIP_TRY(hipMemcpyAsync(c->wallbuf, c->cur, raw.size(), hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(lbm::launch_zero(c->ring, (int64_t)kRing * 4 * 8, c->stream));
+    HIP_TRY(zero_ring(c));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->steps = 0;
     c->pending = false;
@@ -679,6 +751,7 @@ int lbm_set_force_field(lbm_ctx* c, const float* g_device) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (c->pressure && g_device) return fail(LBM_EINVAL, "a force field cannot be combined with pressure faces");
     c->field = g_device;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -694,6 +767,7 @@ int lbm_set_collision(lbm_ctx* c, int collision) {
     }
     const int old = c->collision, old_grid = c->grid;
     c->collision = collision;
+    drop_graphs(c);
     hipError_t he = choose_grid(c);
     if (he != hipSuccess) {
         c->collision = old;
@@ -714,6 +788,7 @@ int lbm_set_wall(lbm_ctx* c, int mode, void* workspace, size_t workspace_bytes) 
     if (mode == LBM_WALL_HALFWAY) {
         c->wall_mode = mode;
         c->wallbuf = nullptr;
+        drop_graphs(c);
         return LBM_OK;
     }
     if (mode != LBM_WALL_FULLWAY) return fail(LBM_EINVAL, "mode must be LBM_WALL_HALFWAY or LBM_WALL_FULLWAY");
@@ -726,6 +801,7 @@ int lbm_set_wall(lbm_ctx* c, int mode, void* workspace, size_t workspace_bytes) 
     // the state one step older than the current one starts equal to it
     HIP_TRY(hipMemcpyAsync(c->wallbuf, c->cur, (size_t)19 * c->np * 4, hipMemcpyDeviceToDevice, c->stream));
     c->wall_mode = mode;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -733,6 +809,7 @@ int lbm_set_pressure(lbm_ctx* c, int enable, double rho_in, double rho_out) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (!enable) {
         c->pressure = false;
+        drop_graphs(c);
         return LBM_OK;
     }
     if (!std::isfinite(rho_in) || !std::isfinite(rho_out) || !(rho_in > 0) || !(rho_out > 0) || rho_in == rho_out)
@@ -744,9 +821,17 @@ int lbm_set_pressure(lbm_ctx* c, int enable, double rho_in, double rho_out) {
     if (c->wall_mode != LBM_WALL_HALFWAY) return fail(LBM_EINVAL, "pressure faces need halfway bounce-back");
     if (c->nx < 3) return fail(LBM_EINVAL, "pressure faces need nx >= 3");
     c->pressure = true;
+    drop_graphs(c);
     c->rho_in = rho_in;
     c->rho_out = rho_out;
     c->axis = 0;
+    return LBM_OK;
+}
+
+int lbm_set_graphs(lbm_ctx* c, int enable) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    c->graphs = enable != 0;
+    if (!c->graphs) drop_graphs(c);
     return LBM_OK;
 }
 
@@ -757,6 +842,7 @@ int lbm_set_storage_exponent(lbm_ctx* c, int e) {
     const float factor = std::ldexp(1.0f, e - c->exponent);
     HIP_TRY(lbm::launch_rescale(c->storage, c->cur, (int64_t)slots(c->storage) * c->np, factor, c->stream));
     c->exponent = e;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -819,7 +905,7 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
 
     // forward from rest to step N, keeping fh^{sK}
     HIP_TRY(lbm::launch_zero(c->cur, (int64_t)19 * c->np * 4, c->stream));
-    HIP_TRY(lbm::launch_zero(c->ring, (int64_t)kRing * 4 * 8, c->stream));
+    HIP_TRY(zero_ring(c));
     c->steps = 0;
     c->pending = false;
     for (int n = 0; n < N; ++n) {

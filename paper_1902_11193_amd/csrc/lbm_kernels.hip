@@ -553,6 +553,25 @@ k_finalize(const double* __restrict__ partials, int grid, double* __restrict__ o
     reduce_partials<K>(partials, grid, out);
 }
 
+// Reduce per-block partials [grid][4] of one step into the next slot of the
+// ring of per-step sums, the slot being the device counter *ctr (steps
+// reduced so far) modulo kRingSlots, then advance the counter.  Run by one
+// whole block; keeping the slot on the device lets a captured sequence of
+// steps replay with unchanged arguments.
+__device__ __forceinline__ void reduce_into_ring(const double* __restrict__ partials, int grid,
+                                                 double* __restrict__ ring, uint32_t* __restrict__ ctr) {
+    const uint32_t slot = ctr[0];
+    reduce_partials<4>(partials, grid, ring + (size_t)(slot % kRingSlots) * 4);
+    __syncthreads();
+    if (threadIdx.x == 0) ctr[0] = slot + 1u;
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_finalize_ring(const double* __restrict__ partials, int grid, double* __restrict__ ring,
+                uint32_t* __restrict__ ctr) {
+    reduce_into_ring(partials, grid, ring, ctr);
+}
+
 // ------------------------------------------------------------------ step
 // Wall links of a node as a bit mask (bit i: the voxel at x - c_i is solid).
 __device__ __forceinline__ uint32_t wall_bits(const int32_t s[19]) {
@@ -578,15 +597,16 @@ __global__ void __launch_bounds__(kThreads)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
        uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
        const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
-       const double* __restrict__ prev_partials, double* __restrict__ prev_out, float* __restrict__ wall,
+       const double* __restrict__ prev_partials, double* __restrict__ ring, uint32_t* __restrict__ ctr,
+       float* __restrict__ wall,
        float drho_in = 0.f, float drho_out = 0.f) {
     using T = typename C::T;
     constexpr int S = C::kSlots;
     constexpr bool REF = C::kRef;
     // The previous step's block partials are reduced here, by the first block,
     // so a time step is a single launch; kernel order makes them visible.
-    if (prev_out != nullptr && blockIdx.x == 0) {
-        reduce_partials<4>(prev_partials, gridDim.x, prev_out);
+    if (prev_partials != nullptr && blockIdx.x == 0) {
+        reduce_into_ring(prev_partials, gridDim.x, ring, ctr);
         __syncthreads();
     }
     const uint32_t lb = logical_block();
@@ -955,11 +975,11 @@ hipError_t step_launch(const StepLaunch& a, Ix ix, hipStream_t s) {
     if (a.field)
         hipLaunchKernelGGL((k_step<C, Ix, true, TRT, FW>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
                            (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
-                           a.inv_scale, a.partials, a.prev_partials, a.prev_out, a.wall);
+                           a.inv_scale, a.partials, a.prev_partials, a.ring, a.ctr, a.wall);
     else
         hipLaunchKernelGGL((k_step<C, Ix, false, TRT, FW>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
                            ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
-                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.prev_out, a.wall);
+                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.ring, a.ctr, a.wall);
     return hipGetLastError();
 }
 
@@ -970,7 +990,7 @@ hipError_t step_pressure(const StepLaunch& a, BitmapIdx ix, hipStream_t s) {
     hipLaunchKernelGGL((k_step<CodecF32, BitmapIdx, false, TRT, false, true>), dim3(a.grid), dim3(kThreads), 0, s,
                        static_cast<const float*>(a.src), static_cast<float*>(a.dst), ix, (uint32_t)a.idx.slack,
                        (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr, a.scale, a.inv_scale, a.partials,
-                       a.prev_partials, a.prev_out, nullptr, a.drho_in, a.drho_out);
+                       a.prev_partials, a.ring, a.ctr, nullptr, a.drho_in, a.drho_out);
     return hipGetLastError();
 }
 
@@ -1051,8 +1071,8 @@ hipError_t step_occupancy(int storage, int index_kind, int collision, int* block
 #undef LBM_OCC
 }
 
-hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_finalize<4>, dim3(1), dim3(kThreads), 0, s, partials, grid, out);
+hipError_t launch_finalize(const double* partials, int grid, double* ring, uint32_t* ctr, hipStream_t s) {
+    hipLaunchKernelGGL(k_finalize_ring, dim3(1), dim3(kThreads), 0, s, partials, grid, ring, ctr);
     return hipGetLastError();
 }
 

@@ -11,6 +11,8 @@ namespace lbm {
 enum Storage : int { kF32 = 0, kF16 = 1, kBF16 = 2, kF16R = 3 };
 enum IndexKind : int { kTable = 0, kBitmap = 1 };
 enum Collision : int { kMrt = 0, kTrt = 1 };
+// Slots of the ring of per-step sums (ux, uy, uz, drho) kept on the device.
+constexpr uint32_t kRingSlots = 1024;
 
 struct RatesF {
     float s_e, s_eps, s_q, s_nu, s_pi, s_m;
@@ -40,8 +42,10 @@ struct StepLaunch {
     float scale, inv_scale;
     int grid;             // number of blocks (fixed per context)
     double* partials;     // [grid][4] written by this step
-    const double* prev_partials;  // [grid][4] of the previous step, reduced by block 0 ...
-    double* prev_out;             // ... into prev_out[0..3]; nullptr: nothing pending
+    const double* prev_partials;  // [grid][4] of the previous step, reduced by block 0 into
+                                  // ring slot (*ctr % kRingSlots), then ++*ctr; nullptr: nothing pending
+    double* ring;                 // [kRingSlots][4] per-step sums
+    uint32_t* ctr;                // steps reduced so far (device)
     float* wall;          // full-way bounce-back: per-node fh of the previous step (state layout,
                           // FP32 storage only), or nullptr for halfway bounce-back
     bool pressure;        // Zou-He pressure faces at x = 0 and x = nx - 1 (FP32, bitmap, no field)
@@ -55,8 +59,8 @@ hipError_t launch_step(const StepLaunch& a, hipStream_t s);
 // Resident blocks per compute unit of the step kernel for this storage/index/collision.
 hipError_t step_occupancy(int storage, int index_kind, int collision, int* blocks_per_cu);
 
-// Sum the per-block partials in fixed order into out[0..3].
-hipError_t launch_finalize(const double* partials, int grid, double* out, hipStream_t s);
+// Sum the per-block partials in fixed order into ring slot (*ctr % kRingSlots), ++*ctr.
+hipError_t launch_finalize(const double* partials, int grid, double* ring, uint32_t* ctr, hipStream_t s);
 
 // Fill count elements of `bytes_per_elem` size with zero bits.
 hipError_t launch_zero(void* p, int64_t bytes, hipStream_t s);
