@@ -9,8 +9,10 @@ launch per step).  Inputs are resident in HBM before timing starts.
 Default workload: the 512^3 Gaussian-random-field rock of porosity 0.20
 (correlation length 6 voxels, x-spanning cluster only), tau = 1, Set E
 Lambda = 3/16, g = 1e-6.  `value` is MFLUPS with FP32 deviation storage; the
-FP16 and BF16 storage paths and the discrete adjoint are timed on the same
-image and reported beside it.
+FP16, BF16 and reference-density FP16 storage paths, the link-wise TRT
+collision and the discrete adjoint are timed on the same image and reported
+beside it.  The library replays its captured step graphs; an untimed run of
+the same call pattern captures them before the timed region.
 """
 from __future__ import annotations
 
