@@ -98,8 +98,9 @@ def run_case(P, mask, rset, tau, Lam, g, eps_paper, eps_tight, max_steps, check_
     import torch
 
     nu = (tau - 0.5) / 3.0
-    s = P.Solver(mask, tau, Lam, rset, (g, 0.0, 0.0), "f32", "bitmap")
-    torch.cuda.synchronize()
+    s = P.Solver(mask, tau, Lam, rset, (g, 0.0, 0.0), "f32", "bitmap")   # on the caller's current stream
+    stream = torch.cuda.current_stream()
+    stream.synchronize()
     t0 = time.perf_counter()
     it_paper = it_mean2 = None
     k_at_paper = None
@@ -129,13 +130,37 @@ def run_case(P, mask, rset, tau, Lam, g, eps_paper, eps_tight, max_steps, check_
         alt = float(np.abs(u[-1] - u[-2]) / np.abs(m2[-1]))
     u = s.history(2)[:, 0]
     k = float(nu * 0.5 * (u[0] + u[1]) / g)
-    torch.cuda.synchronize()
+    stream.synchronize()
     t = time.perf_counter() - t0
     nf = s.n_fluid
     s.close()
     return dict(k=k, k_at_paper_test=k_at_paper, iterations_paper=it_paper, iterations_mean2=it_mean2,
                 steps=done, converged_tight=conv, period2_amplitude=alt, seconds=t, MFLUPS=nf * done / t / 1e6,
                 n_fluid=nf)
+
+
+def run_all(P, jobs, workers):
+    """Run independent cases concurrently, each worker thread on a stream of
+    its own (default priority): small images leave most of the GPU idle, so
+    their steps overlap.  Returns the results in job order."""
+    import threading
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+
+    tls = threading.local()
+
+    def one(job):
+        if not hasattr(tls, "stream"):
+            torch.cuda.set_device(0)
+            tls.stream = torch.cuda.Stream()
+        with torch.cuda.stream(tls.stream):
+            return job()
+
+    if workers <= 1:
+        return [job() for job in jobs]
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(one, jobs))
 
 
 def emit(rec, fh):
@@ -190,6 +215,8 @@ def main():
     ap.add_argument("--eps-tight", type=float, default=1e-9)
     ap.add_argument("--max-steps", type=int, default=400000)
     ap.add_argument("--out", default="")
+    ap.add_argument("--workers", type=int, default=4,
+                    help="cases run concurrently, one stream each (1: one after the other)")
     args = ap.parse_args()
 
     import torch
@@ -203,13 +230,20 @@ def main():
     if args.what == "sets":
         for name, mask, kref, half in geometries(args.geoms):
             print(f"[study] {name}: {int((mask == 0).sum())} fluid nodes", file=sys.stderr, flush=True)
+            meta, jobs = [], []
             for label, rset, lam in set_variants(args.sets):
                 for tau in taus:
                     g = channel_force(tau, half) if half else 1e-6
-                    r = run_case(P, mask, rset, tau, lam, g, args.eps_paper, args.eps_tight, args.max_steps)
-                    r.update(geometry=name, label=label, set=rset, Lambda=lam, tau=tau, g=g, k_ref=kref)
-                    records.append(r)
-                    emit(r, fh)
+                    meta.append(dict(geometry=name, label=label, set=rset, Lambda=lam, tau=tau, g=g, k_ref=kref))
+                    jobs.append(lambda rset=rset, tau=tau, lam=lam, g=g: run_case(
+                        P, mask, rset, tau, lam, g, args.eps_paper, args.eps_tight, args.max_steps))
+            t0 = time.perf_counter()
+            for m_, r in zip(meta, run_all(P, jobs, args.workers)):
+                r.update(m_)
+                records.append(r)
+                emit(r, fh)
+            print(f"[study] {name}: {len(jobs)} runs in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                  flush=True)
     elif args.what == "resolution":
         from lbm_inputs import pipe
 
