@@ -93,7 +93,8 @@ extern "C" {
  * LBM_INDEX_BITMAP: one packed uint32 voxel coordinate per node plus, for
  *                   every (y, z) row, a 16-byte record per 32 voxels (fluid
  *                   bits, node number before the word, fluid count of the
- *                   row); the source node of a link is found by a population
+ *                   row, fluid bits of the next word); the source node of a
+ *                   link is found by a population
  *                   count.  4 bytes per node + 4 bits per voxel.  Needs
  *                   ceil(log2 nx) + ceil(log2 ny) + ceil(log2 nz) <= 32. */
 #define LBM_INDEX_TABLE 0

@@ -265,12 +265,13 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                     rr[w].bits = bits;
                     rr[w].base = (int32_t)(rowstart + before - (w == 0 ? pad[0] : 0));
                     rr[w].count = count;
-                    rr[w].unused = 0;
+                    rr[w].next = 0;
                     for (int b = 0; b < kRecBits; ++b) {
                         const int q = kRecBits * w + b;
                         if (q >= 1 && q <= nx) before += pad[q];
                     }
                 }
+                for (int w = 0; w + 1 < R; ++w) rr[w].next = rr[w + 1].bits;
                 for (int x = 0; x < nx; ++x)
                     if (p[x] == 0)
                         out->coords[n++] =

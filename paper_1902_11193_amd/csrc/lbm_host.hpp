@@ -79,16 +79,17 @@ void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_
 // Bitmap index.  Every (y, z) row of the image is a padded bit string of
 // nx + 2 positions: position x + 1 holds voxel x, position 0 repeats voxel
 // nx - 1 and position nx + 1 repeats voxel 0 (the periodic wrap).  It is cut
-// into 32-position words; each word has a 16-byte record with its bits, the
-// node number counting real voxels before the word (minus the left pad bit
-// on word 0) and the row's fluid count.  One extra zero record ends each row
-// so that a 3-position window never reads past it.  Each node also keeps its
+// into 32-position words; each word has a 16-byte record with its bits, a
+// copy of the next word's bits (so a 3-position window that crosses into the
+// next word needs no second load), the node number counting real voxels
+// before the word (minus the left pad bit on word 0) and the row's fluid
+// count.  One extra zero record ends each row.  Each node also keeps its
 // packed voxel coordinate.
 struct RowRec {
     uint32_t bits;
+    uint32_t next;  // bits of the following record of the row (0 on the last)
     int32_t base;
-    int32_t count;
-    int32_t unused;
+    int32_t count;  // last, so a row read without the x wrap is one 12-byte load
 };
 static_assert(sizeof(RowRec) == 16, "RowRec is one 16-byte load");
 constexpr int kRecBits = 32;

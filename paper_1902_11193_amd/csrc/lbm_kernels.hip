@@ -168,12 +168,23 @@ __device__ __forceinline__ void gather_offsets(const int32_t s[19], uint32_t n, 
 
 // ------------------------------------------------------------------ indices
 // An index yields, for node n, the pull sources s[i] (i = 1..18): the node
-// at x_n - c_i, or -1 when that voxel is solid (halfway bounce-back there).
-// The adjoint reads them transposed, s[opp(i)] being the node at x_n + c_i.
+// at x_n - c_i, or -1 when that voxel is solid (halfway bounce-back there),
+// and from them the 19 gather offsets of the step (offsets).  The adjoint
+// reads the sources transposed, s[opp(i)] being the node at x_n + c_i.
 //
 // Both indices split into load (issue the memory reads for a node) and
 // resolve (arithmetic on what was read), so a caller can overlap the reads of
 // one node with the population traffic of another.
+
+// Wall links of a node as a bit mask (bit i: the voxel at x - c_i is solid).
+__device__ __forceinline__ uint32_t wall_bits(const int32_t s[19]) {
+    uint32_t b = 0;
+    unroll<18>([&](auto k) {
+        constexpr int i = decltype(k)::value + 1;
+        b |= (uint32_t)(s[i] < 0) << i;
+    });
+    return b;
+}
 
 // Device table of pull sources [18][stride] (entry -1: solid source).
 struct TableIdx {
@@ -196,11 +207,21 @@ struct TableIdx {
             s[i] = r.t[i];
         });
     }
+    // gather offsets of node n (chunk `chunk`) and, if WB, its wall links
+    template <class T, int S, bool WB>
+    __device__ __forceinline__ void offsets(const Raw& r, Pre p, uint32_t n, uint32_t chunk,
+                                            uint32_t slack, uint32_t off[19], uint32_t& wb) const {
+        int32_t s[19];
+        sources(r, p, s);
+        gather_offsets<T, S>(s, n, chunk, slack, off);
+        if constexpr (WB) wb = wall_bits(s);
+    }
 };
 
 // Row-word records of the padded bit strings built on the host: 32 padded
-// positions per 16-byte record {bits, base, count, 0}; position x + 1 is
-// voxel x and the two ends repeat the opposite voxel (periodic x).
+// positions per 16-byte record {bits, bits of the next record, base, count};
+// position x + 1 is voxel x and the two ends repeat the opposite voxel
+// (periodic x).  One 16-byte load per row gives everything a node needs.
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
     const uint4* __restrict__ rec;
@@ -213,9 +234,9 @@ struct BitmapIdx {
         const uint4 a = ld_off(rec, off);
         RowRaw w;
         w.bits = a.x;
-        w.base = a.y;
-        w.count = a.z;
-        w.next = ld_off(reinterpret_cast<const uint32_t*>(rec), off + 16u);
+        w.next = a.y;
+        w.base = a.z;
+        w.count = a.w;
         return w;
     }
     // voxels x - 1, x, x + 1 of a row: fluid bits (bit 0..2) and node numbers
@@ -302,6 +323,56 @@ struct BitmapIdx {
         s[16] = pick(decode(r.pp, x, xf, xl), 0);
         s[17] = pick(decode(r.mp, x, xf, xl), 0);
         s[18] = pick(decode(r.pm, x, xf, xl), 0);
+    }
+    // Gather offsets of node n straight from the decoded rows: for each
+    // direction the fluid bit of the source voxel selects, bitwise, between
+    // the pulled population and the node's own opposite one, so no node
+    // number -1 is formed and tested.  WB: also the wall links as a mask.
+    template <class T, int S, bool WB>
+    __device__ __forceinline__ void offsets(const Raw& r, Pre c, uint32_t n, uint32_t chunk,
+                                            uint32_t slack, uint32_t off[19], uint32_t& wb) const {
+        constexpr uint32_t sz = sizeof(T);
+        const uint32_t x = c & ((1u << bx) - 1u);
+        const bool xf = x == 0, xl = x == nx - 1;
+        const uint32_t kb = chunk_kb<T, S>(chunk, slack);
+        const uint32_t ekb = node_elem<S>(n) * sz + kb;
+        off[0] = ekb;
+        uint32_t walls = 0;
+        auto put = [&](auto I, const Row3& w, int which) {
+            constexpr int i = decltype(I)::value;
+            const uint32_t v = (uint32_t)(which < 0 ? w.rm : (which == 0 ? w.r0 : w.rp));
+            // all ones when the source voxel is fluid
+            const uint32_t fluid = (uint32_t)__builtin_amdgcn_sbfe((int32_t)w.bits, (uint32_t)(which + 1), 1u);
+            const uint32_t pulled = node_elem<S>(v) * sz + (kb + (uint32_t)i * kThreads * sz);
+            const uint32_t own = ekb + (uint32_t)opp(i) * kThreads * sz;
+            off[i] = (pulled & fluid) | (own & ~fluid);
+            if constexpr (WB) walls |= ~fluid & (1u << i);
+        };
+        using std::integral_constant;
+        const Row3 o = decode(r.own, x, xf, xl);
+        put(integral_constant<int, 1>{}, o, -1);
+        put(integral_constant<int, 2>{}, o, +1);
+        const Row3 a = decode(r.ym, x, xf, xl);
+        put(integral_constant<int, 3>{}, a, 0);
+        put(integral_constant<int, 7>{}, a, -1);
+        put(integral_constant<int, 10>{}, a, +1);
+        const Row3 b = decode(r.yp, x, xf, xl);
+        put(integral_constant<int, 4>{}, b, 0);
+        put(integral_constant<int, 8>{}, b, +1);
+        put(integral_constant<int, 9>{}, b, -1);
+        const Row3 d = decode(r.zm, x, xf, xl);
+        put(integral_constant<int, 5>{}, d, 0);
+        put(integral_constant<int, 11>{}, d, -1);
+        put(integral_constant<int, 14>{}, d, +1);
+        const Row3 e = decode(r.zp, x, xf, xl);
+        put(integral_constant<int, 6>{}, e, 0);
+        put(integral_constant<int, 12>{}, e, +1);
+        put(integral_constant<int, 13>{}, e, -1);
+        put(integral_constant<int, 15>{}, decode(r.mm, x, xf, xl), 0);
+        put(integral_constant<int, 16>{}, decode(r.pp, x, xf, xl), 0);
+        put(integral_constant<int, 17>{}, decode(r.mp, x, xf, xl), 0);
+        put(integral_constant<int, 18>{}, decode(r.pm, x, xf, xl), 0);
+        if constexpr (WB) wb = walls;
     }
 };
 
@@ -573,16 +644,6 @@ k_finalize_ring(const double* __restrict__ partials, int grid, double* __restric
 }
 
 // ------------------------------------------------------------------ step
-// Wall links of a node as a bit mask (bit i: the voxel at x - c_i is solid).
-__device__ __forceinline__ uint32_t wall_bits(const int32_t s[19]) {
-    uint32_t b = 0;
-    unroll<18>([&](auto k) {
-        constexpr int i = decltype(k)::value + 1;
-        b |= (uint32_t)(s[i] < 0) << i;
-    });
-    return b;
-}
-
 // FW: full-way bounce-back (Sec. 2.2).  A population sent into a wall comes
 // back one step later than with the halfway wall, so at a wall link the node
 // takes fh_opp(i) of two steps ago.  `wall` keeps, per node and population p,
@@ -630,10 +691,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
-            int32_t s[19];
-            ix.sources(raw, p0, s);
-            gather_offsets<T, S>(s, n, c, slack, off);
-            if constexpr (FW || REF) wb = wall_bits(s);
+            ix.template offsets<T, S, FW || REF>(raw, p0, n, c, slack, off, wb);
             if constexpr (ZH) side = ix.x_face(p0);
         }
         for (;;) {
@@ -676,10 +734,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             __builtin_amdgcn_sched_barrier(0);
             const uint32_t wb_n = wb, side_n = side;
             {
-                int32_t s[19];
-                ix.sources(raw, pre1, s);
-                gather_offsets<T, S>(s, n1, c + G, slack, off);
-                if constexpr (FW || REF) wb = wall_bits(s);
+                ix.template offsets<T, S, FW || REF>(raw, pre1, n1, c + G, slack, off, wb);
                 if constexpr (ZH) side = ix.x_face(pre1);
             }
             __builtin_amdgcn_sched_barrier(0);
