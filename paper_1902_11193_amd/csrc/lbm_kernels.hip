@@ -75,11 +75,8 @@ struct CodecBF16 {
     static __device__ __forceinline__ float cvt(T v, float inv) {
         return __uint_as_float((uint32_t)v << 16) * inv;
     }
-    static __device__ __forceinline__ T enc(float v, float s) {
-        const uint32_t u = __float_as_uint(v * s);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return (T)((u >> 16) | 0x40u);  // quiet NaN
-        return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);               // nearest even
-    }
+    // round to nearest even (NaN stays NaN): one hardware conversion on gfx950
+    static __device__ __forceinline__ T enc(float v, float s) { return __builtin_bit_cast(T, (__bf16)(v * s)); }
 };
 
 // FP16 relative to a per-node reference density: a node stores, besides its
