@@ -193,6 +193,27 @@ def test_gather_span_bounds_brute_force(tmp_path):
     assert "bad 0" in r.stdout
 
 
+def test_bitmap_records_decode_to_neighbour_table(tmp_path):
+    """The bitmap index (packed coordinate per node, one 16-byte record per
+    32 voxels of each row with the next word's bits) decodes, by the step
+    kernel's arithmetic modelled on the CPU, to exactly the pull sources of
+    the neighbour table on random periodic images, including row lengths
+    around the 32-voxel word size."""
+    import shutil
+    import subprocess
+    gxx = shutil.which("g++")
+    if gxx is None:
+        pytest.skip("g++ not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    csrc = os.path.join(root, "paper_1902_11193_amd", "csrc")
+    exe = tmp_path / "check_bitmap"
+    subprocess.run([gxx, "-O2", "-std=c++17", "-I", csrc, os.path.join(root, "tests", "host", "check_bitmap.cpp"),
+                    os.path.join(csrc, "lbm_host.cpp"), "-o", str(exe), "-lpthread"], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "bad 0" in r.stdout
+
+
 @pytest.mark.parametrize("shape,pad,my,mz", [((3, 4, 5), 2, True, True), ((4, 3, 6), 5, False, True),
                                              ((2, 5, 3), 0, True, False), ((3, 3, 3), 1, False, False)])
 def test_boundary_image_pads_and_mirrors(shape, pad, my, mz):
