@@ -30,8 +30,16 @@ METRIC = "MFLUPS & %HBM peak, D3Q19-MRT 512^3 pack: fp32 vs fp16-store vs adjoin
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per fluid-lattice update: 19 populations read + 19 written.
 ALG_BYTES = {"f32": 19 * 4 * 2, "f16": 19 * 2 * 2, "bf16": 19 * 2 * 2, "f16r": 20 * 2 * 2}
-# Index bytes per node the design adds: int32 [18] table, or one packed coordinate.
-INDEX_BYTES = {"table": 18 * 4, "bitmap": 4}
+# Index bytes per node the design adds: the int32 [18] table; or, for the bitmap,
+# one packed coordinate per node plus the row records read once per step
+# (8 bytes per 20 voxels of a row, stored three times: 24 * ny * nz * words).
+
+
+def index_bytes(index: str, shape, nf: int) -> float:
+    if index == "table":
+        return 18 * 4
+    nz, ny, nx = shape
+    return 4 + 24 * ny * nz * ((nx + 19) // 20) / nf
 # Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n.
 ADJ_ALG_BYTES = 3 * 19 * 4
 
@@ -89,7 +97,7 @@ def run_forward(P, mask, args, storage, collision="mrt"):
     torch.cuda.empty_cache()
     mflups = nf / (ms * 1e-3) / 1e6
     alg_gbs = ALG_BYTES[storage] * nf / (ms * 1e-3) / 1e9
-    des_gbs = (ALG_BYTES[storage] + INDEX_BYTES[args.index]) * nf / (ms * 1e-3) / 1e9
+    des_gbs = (ALG_BYTES[storage] + index_bytes(args.index, mask.shape, nf)) * nf / (ms * 1e-3) / 1e9
     voxel_mlups = mask.size / (ms * 1e-3) / 1e6   # per voxel of the image, as dense codes count
     return dict(ms_per_step=ms, MFLUPS=mflups, MLUPS_per_voxel=voxel_mlups, GBps_algorithmic=alg_gbs,
                 GBps_designed=des_gbs,

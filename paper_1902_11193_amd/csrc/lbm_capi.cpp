@@ -63,7 +63,7 @@ Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int n
         L.table = off;
         off += align256((size_t)18 * np * 4);
     } else {
-        const size_t recs = (size_t)ny * nz * lbm::records_per_row(nx);
+        const size_t recs = (size_t)ny * nz * lbm::words_per_row(nx) * 3;
         L.coords = off;
         off += align256((size_t)std::max<int64_t>(nf, 1) * 4);
         L.rec = off;
@@ -342,6 +342,10 @@ int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int sto
     if (nf >= ((int64_t)1 << 31) - 256) return fail(LBM_ERANGE, "more than 2^31 fluid nodes");
     if (index_kind == LBM_INDEX_BITMAP && !lbm::coord_bits(nx, ny, nz).fits())
         return fail(LBM_ERANGE, "packed voxel coordinates need more than 32 bits");
+    if (index_kind == LBM_INDEX_BITMAP && nf > lbm::kBitmapMaxNodes)
+        return fail(LBM_ERANGE, "the bitmap index holds at most 2^30 - 2 fluid nodes");
+    if (index_kind == LBM_INDEX_BITMAP && (int64_t)ny * nz * lbm::words_per_row(nx) >= ((int64_t)1 << 32))
+        return fail(LBM_ERANGE, "the bitmap index holds fewer than 2^32 row words");
     e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, slots(storage)), storage);
     if (!e.empty()) return fail(LBM_ERANGE, e);
     if (bytes) *bytes = layout(lbm::padded(nf), nf, storage, index_kind, nx, ny, nz).total;
@@ -513,7 +517,7 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
         v.nx = nx;
         v.ny = ny;
         v.nz = nz;
-        v.R = bm.recs_per_row;
+        v.R = bm.words;
         v.bx = bm.bits.bx;
         v.by = bm.bits.by;
         he = hipMemcpyAsync(c->ws + c->L.coords, bm.coords.data(), bm.coords.size() * 4,

@@ -233,15 +233,14 @@ void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t s
 }
 
 void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out) {
-    const int R = records_per_row(nx);
-    const int64_t rows = (int64_t)ny * nz;
-    out->recs_per_row = R;
+    const int W = words_per_row(nx);
+    out->words = W;
     out->bits = coord_bits(nx, ny, nz);
     out->coords.assign(nf, 0);
-    out->rec.assign(rows * R, RowRec{0, 0, 0, 0});
+    out->rec.assign((size_t)nz * ny * W * 3, RowRec{0, 0});
     auto start = row_starts(g, nx, ny, nz);
     const int bx = out->bits.bx, by = out->bits.by;
-    parallel_slabs(nz, rows * nx, [&](int z0, int z1) {
+    parallel_slabs(nz, (int64_t)ny * nz * nx, [&](int z0, int z1) {
         std::vector<uint8_t> pad(nx + 2);
         for (int z = z0; z < z1; ++z)
             for (int y = 0; y < ny; ++y) {
@@ -252,26 +251,28 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                 for (int x = 0; x < nx; ++x) pad[x + 1] = p[x] == 0;
                 pad[0] = pad[nx];
                 pad[nx + 1] = pad[1];
-                int32_t count = 0;
+                uint32_t count = 0;
                 for (int x = 0; x < nx; ++x) count += pad[x + 1];
-                RowRec* rr = out->rec.data() + r * R;
-                int64_t before = 0;  // fluid voxels at real positions [1, 32 w)
-                for (int w = 0; w < R; ++w) {
+                int64_t before = 0;  // fluid voxels at real positions [1, kWordStep w)
+                for (int w = 0; w < W; ++w) {
                     uint32_t bits = 0;
-                    for (int b = 0; b < kRecBits; ++b) {
-                        const int q = kRecBits * w + b;
+                    for (int b = 0; b < kWordStep + 2; ++b) {
+                        const int q = kWordStep * w + b;
                         if (q < nx + 2 && pad[q]) bits |= 1u << b;
                     }
-                    rr[w].bits = bits;
-                    rr[w].base = (int32_t)(rowstart + before - (w == 0 ? pad[0] : 0));
-                    rr[w].count = count;
-                    rr[w].next = 0;
-                    for (int b = 0; b < kRecBits; ++b) {
-                        const int q = kRecBits * w + b;
+                    const int64_t base = rowstart + before - (w == 0 ? pad[0] : 0);
+                    const RowRec rr{bits | (count & 0x3ffu) << 22, (uint32_t)(base + 1) | (count >> 10) << 30};
+                    // this row is row y of its own triple, row y + 1 of row
+                    // y - 1's and row y - 1 of row y + 1's (periodic in y; with
+                    // ny <= 2 one triple takes it in two or three slots)
+                    const int yn[3] = {(y + 1) % ny, y, (y + ny - 1) % ny};
+                    for (int k = 0; k < 3; ++k)
+                        out->rec[(((int64_t)z * ny + yn[k]) * W + w) * 3 + k] = rr;
+                    for (int b = 0; b < kWordStep; ++b) {
+                        const int q = kWordStep * w + b;
                         if (q >= 1 && q <= nx) before += pad[q];
                     }
                 }
-                for (int w = 0; w + 1 < R; ++w) rr[w].next = rr[w + 1].bits;
                 for (int x = 0; x < nx; ++x)
                     if (p[x] == 0)
                         out->coords[n++] =

@@ -78,27 +78,31 @@ void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_
 
 // Bitmap index.  Every (y, z) row of the image is a padded bit string of
 // nx + 2 positions: position x + 1 holds voxel x, position 0 repeats voxel
-// nx - 1 and position nx + 1 repeats voxel 0 (the periodic wrap).  It is cut
-// into 32-position words; each word has a 16-byte record with its bits, a
-// copy of the next word's bits (so a 3-position window that crosses into the
-// next word needs no second load), the node number counting real voxels
-// before the word (minus the left pad bit on word 0) and the row's fluid
-// count.  One extra zero record ends each row.  Each node also keeps its
+// nx - 1 and position nx + 1 repeats voxel 0 (the periodic wrap).  Word w of a
+// row covers positions kWordStep w .. kWordStep w + 21: consecutive words
+// overlap by two positions, so the window x .. x + 2 (voxels x - 1, x, x + 1)
+// of voxel x lies inside word x / kWordStep.  A word's 8-byte record packs its
+// 22 bits, the row's fluid count and one plus the node number counting real
+// voxels before the word (minus the left pad bit on word 0).  For every row
+// (y, z) and word w the array holds the records of rows y - 1, y, y + 1
+// (periodic in y) of plane z side by side, 24 bytes, stored by (z, y, w): a
+// node reads its nine rows with one 16-byte and one 8-byte load per plane,
+// and the nodes of a row read consecutive bytes.  Each node also keeps its
 // packed voxel coordinate.
+constexpr int kWordStep = 20;
 struct RowRec {
-    uint32_t bits;
-    uint32_t next;  // bits of the following record of the row (0 on the last)
-    int32_t base;
-    int32_t count;  // last, so a row read without the x wrap is one 12-byte load
+    uint32_t lo;  // bits 0..21: the word's positions; bits 22..31: count & 0x3ff
+    uint32_t hi;  // bits 0..29: base + 1; bits 30..31: count >> 10
 };
-static_assert(sizeof(RowRec) == 16, "RowRec is one 16-byte load");
-constexpr int kRecBits = 32;
-inline int records_per_row(int nx) { return (nx + 2 + kRecBits - 1) / kRecBits + 1; }
+static_assert(sizeof(RowRec) == 8, "RowRec is one 8-byte record");
+inline int words_per_row(int nx) { return (nx - 1) / kWordStep + 1; }
+// largest fluid-node count whose record bases fit their 30 bits
+constexpr int64_t kBitmapMaxNodes = ((int64_t)1 << 30) - 2;
 struct BitmapIndex {
-    int recs_per_row = 0;
+    int words = 0;  // records per row
     CoordBits bits{};
     std::vector<uint32_t> coords;  // [nf]
-    std::vector<RowRec> rec;       // [ny * nz * recs_per_row]
+    std::vector<RowRec> rec;       // [nz][ny][words][3]: rows y - 1, y, y + 1
 };
 void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out);
 

@@ -215,40 +215,33 @@ struct TableIdx {
     }
 };
 
-// Row-word records of the padded bit strings built on the host: 32 padded
-// positions per 16-byte record {bits, bits of the next record, base, count};
-// position x + 1 is voxel x and the two ends repeat the opposite voxel
-// (periodic x).  One 16-byte load per row gives everything a node needs.
+// Row-word records of the padded bit strings built on the host: word w of a
+// row covers padded positions 20 w .. 20 w + 21 (position x + 1 is voxel x,
+// the two ends repeat the opposite voxel: periodic x), so the window of voxel
+// x lies in word x / 20.  A record is 8 bytes {22 bits | count low 10 bits,
+// base + 1 | count high 2 bits}; entry (z, y, w) holds the records of rows
+// y - 1, y, y + 1 of plane z, 24 bytes: one 16-byte and one 8-byte load.
+constexpr uint32_t kWordStep = 20;
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
-    const uint4* __restrict__ rec;
-    uint32_t nx, ny, nz, R, bx, by;
+    const uint2* __restrict__ rec;
+    uint32_t nx, ny, nz, R, bx, by;  // R: words per row
 
-    struct RowRaw {
-        uint32_t bits, base, count, next;  // record of word x >> 5, low bits of the next
-    };
-    __device__ __forceinline__ RowRaw row_at(uint32_t off) const {
-        const uint4 a = ld_off(rec, off);
-        RowRaw w;
-        w.bits = a.x;
-        w.next = a.y;
-        w.base = a.z;
-        w.count = a.w;
-        return w;
-    }
     // voxels x - 1, x, x + 1 of a row: fluid bits (bit 0..2) and node numbers
     struct Row3 {
         int32_t rm, r0, rp;
         uint32_t bits;
     };
-    __device__ __forceinline__ Row3 decode(const RowRaw& w, uint32_t x, bool x_first, bool x_last) const {
-        const uint32_t sh = x & 31u;
+    __device__ __forceinline__ Row3 decode(uint2 rec8, uint32_t x, bool x_first, bool x_last) const {
+        const uint32_t lo = rec8.x, hi = rec8.y;
+        const uint32_t sh = x - (x / kWordStep) * kWordStep;
+        const int32_t count = (int32_t)((lo >> 22) | ((hi >> 30) << 10));
         Row3 r;
-        r.bits = __builtin_amdgcn_alignbit(w.next, w.bits, sh) & 7u;   // padded positions x..x+2
-        const int32_t below = (int32_t)__popc(__builtin_amdgcn_ubfe(w.bits, 0u, sh));
-        r.r0 = (int32_t)w.base + below + (int32_t)(r.bits & 1u);
-        r.rm = r.r0 - 1 + (x_first ? (int32_t)w.count : 0);
-        r.rp = r.r0 + (int32_t)((r.bits >> 1) & 1u) - (x_last ? (int32_t)w.count : 0);
+        r.bits = __builtin_amdgcn_ubfe(lo, sh, 3u);   // padded positions x..x+2
+        const int32_t below = (int32_t)__popc(__builtin_amdgcn_ubfe(lo, 0u, sh));
+        r.r0 = (int32_t)(hi & 0x3fffffffu) - 1 + below + (int32_t)(r.bits & 1u);
+        r.rm = r.r0 - 1 + (x_first ? count : 0);
+        r.rp = r.r0 + (int32_t)((r.bits >> 1) & 1u) - (x_last ? count : 0);
         return r;
     }
     using Pre = uint32_t;  // the node's packed coordinate, loaded ahead of use
@@ -258,34 +251,40 @@ struct BitmapIdx {
         const uint32_t x = c & ((1u << bx) - 1u);
         return x == 0 ? 1u : (x == nx - 1 ? 2u : 0u);
     }
+    // per plane z - 1, z, z + 1: rows y - 1 and y (a), row y + 1 (b)
     struct Raw {
-        RowRaw own, ym, yp, zm, zp, mm, pp, mp, pm;
+        uint4 a[3];
+        uint2 b[3];
+        // the nine rows around the node: (y, z) and its y / z neighbours
+        __device__ __forceinline__ uint2 own() const { return make_uint2(a[1].z, a[1].w); }
+        __device__ __forceinline__ uint2 ym() const { return make_uint2(a[1].x, a[1].y); }
+        __device__ __forceinline__ uint2 yp() const { return b[1]; }
+        __device__ __forceinline__ uint2 zm() const { return make_uint2(a[0].z, a[0].w); }
+        __device__ __forceinline__ uint2 zp() const { return make_uint2(a[2].z, a[2].w); }
+        __device__ __forceinline__ uint2 mm() const { return make_uint2(a[0].x, a[0].y); }  // y - 1, z - 1
+        __device__ __forceinline__ uint2 pm() const { return b[0]; }                        // y + 1, z - 1
+        __device__ __forceinline__ uint2 mp() const { return make_uint2(a[2].x, a[2].y); }  // y - 1, z + 1
+        __device__ __forceinline__ uint2 pp() const { return b[2]; }                        // y + 1, z + 1
     };
-    // issue the nine row-record loads of the node with packed coordinate c
+    // issue the six record loads of the node with packed coordinate c
     __device__ __forceinline__ void load(uint32_t, Pre c, Raw& r) const {
         const uint32_t x = c & ((1u << bx) - 1u);
         const uint32_t y = (c >> bx) & ((1u << by) - 1u);
         const uint32_t z = (uint32_t)((uint64_t)c >> (bx + by));
-        const uint32_t rowb = R * 16u, planeb = ny * rowb;
-        const uint32_t o = ((z * ny + y) * R + (x >> 5)) * 16u;
-        // byte steps to the rows y - 1, y + 1, z - 1, z + 1 (periodic)
-        const uint32_t dym = y == 0 ? (ny - 1) * rowb : 0u - rowb;
-        const uint32_t dyp = y == ny - 1 ? 0u - (ny - 1) * rowb : rowb;
-        const uint32_t dzm = z == 0 ? (nz - 1) * planeb : 0u - planeb;
-        const uint32_t dzp = z == nz - 1 ? 0u - (nz - 1) * planeb : planeb;
-        const uint32_t o1 = o + dym, o2 = o + dyp, o3 = o + dzm, o4 = o + dzp, o5 = o3 + dym,
-                       o6 = o4 + dyp, o7 = o4 + dym, o8 = o3 + dyp;
-        // all addresses first, then the loads back to back
+        const uint32_t plane = ny * R;                          // entries per plane
+        const uint32_t e = (z * ny + y) * R + x / kWordStep;    // entry (z, y, w)
+        const uint32_t em = e + (z == 0 ? (nz - 1) * plane : 0u - plane);
+        const uint32_t ep = e + (z == nz - 1 ? 0u - (nz - 1) * plane : plane);
+        const uint2* pm = rec + (uint64_t)em * 3u;
+        const uint2* p0 = rec + (uint64_t)e * 3u;
+        const uint2* pp = rec + (uint64_t)ep * 3u;
         __builtin_amdgcn_sched_barrier(0);
-        r.own = row_at(o);
-        r.ym = row_at(o1);
-        r.yp = row_at(o2);
-        r.zm = row_at(o3);
-        r.zp = row_at(o4);
-        r.mm = row_at(o5);
-        r.pp = row_at(o6);
-        r.mp = row_at(o7);
-        r.pm = row_at(o8);
+        r.a[0] = *reinterpret_cast<const uint4*>(pm);
+        r.b[0] = pm[2];
+        r.a[1] = *reinterpret_cast<const uint4*>(p0);
+        r.b[1] = p0[2];
+        r.a[2] = *reinterpret_cast<const uint4*>(pp);
+        r.b[2] = pp[2];
     }
     // pull sources s[i] (node number or -1) from the decoded rows
     __device__ __forceinline__ void sources(const Raw& r, Pre c, int32_t s[19]) const {
@@ -297,29 +296,29 @@ struct BitmapIdx {
             return bit ? v : -1;
         };
         // source x' = x - c_x: c_x = +1 reads x - 1 (which -1), c_x = -1 reads x + 1
-        const Row3 o = decode(r.own, x, xf, xl);
+        const Row3 o = decode(r.own(), x, xf, xl);
         s[1] = pick(o, -1);
         s[2] = pick(o, +1);
-        const Row3 a = decode(r.ym, x, xf, xl);   // c_y = +1
+        const Row3 a = decode(r.ym(), x, xf, xl);   // c_y = +1
         s[3] = pick(a, 0);
         s[7] = pick(a, -1);
         s[10] = pick(a, +1);
-        const Row3 b = decode(r.yp, x, xf, xl);   // c_y = -1
+        const Row3 b = decode(r.yp(), x, xf, xl);   // c_y = -1
         s[4] = pick(b, 0);
         s[8] = pick(b, +1);
         s[9] = pick(b, -1);
-        const Row3 d = decode(r.zm, x, xf, xl);   // c_z = +1
+        const Row3 d = decode(r.zm(), x, xf, xl);   // c_z = +1
         s[5] = pick(d, 0);
         s[11] = pick(d, -1);
         s[14] = pick(d, +1);
-        const Row3 e = decode(r.zp, x, xf, xl);   // c_z = -1
+        const Row3 e = decode(r.zp(), x, xf, xl);   // c_z = -1
         s[6] = pick(e, 0);
         s[12] = pick(e, +1);
         s[13] = pick(e, -1);
-        s[15] = pick(decode(r.mm, x, xf, xl), 0);
-        s[16] = pick(decode(r.pp, x, xf, xl), 0);
-        s[17] = pick(decode(r.mp, x, xf, xl), 0);
-        s[18] = pick(decode(r.pm, x, xf, xl), 0);
+        s[15] = pick(decode(r.mm(), x, xf, xl), 0);
+        s[16] = pick(decode(r.pp(), x, xf, xl), 0);
+        s[17] = pick(decode(r.mp(), x, xf, xl), 0);
+        s[18] = pick(decode(r.pm(), x, xf, xl), 0);
     }
     // Gather offsets of node n straight from the decoded rows: for each
     // direction the fluid bit of the source voxel selects, bitwise, between
@@ -346,29 +345,29 @@ struct BitmapIdx {
             if constexpr (WB) walls |= ~fluid & (1u << i);
         };
         using std::integral_constant;
-        const Row3 o = decode(r.own, x, xf, xl);
+        const Row3 o = decode(r.own(), x, xf, xl);
         put(integral_constant<int, 1>{}, o, -1);
         put(integral_constant<int, 2>{}, o, +1);
-        const Row3 a = decode(r.ym, x, xf, xl);
+        const Row3 a = decode(r.ym(), x, xf, xl);
         put(integral_constant<int, 3>{}, a, 0);
         put(integral_constant<int, 7>{}, a, -1);
         put(integral_constant<int, 10>{}, a, +1);
-        const Row3 b = decode(r.yp, x, xf, xl);
+        const Row3 b = decode(r.yp(), x, xf, xl);
         put(integral_constant<int, 4>{}, b, 0);
         put(integral_constant<int, 8>{}, b, +1);
         put(integral_constant<int, 9>{}, b, -1);
-        const Row3 d = decode(r.zm, x, xf, xl);
+        const Row3 d = decode(r.zm(), x, xf, xl);
         put(integral_constant<int, 5>{}, d, 0);
         put(integral_constant<int, 11>{}, d, -1);
         put(integral_constant<int, 14>{}, d, +1);
-        const Row3 e = decode(r.zp, x, xf, xl);
+        const Row3 e = decode(r.zp(), x, xf, xl);
         put(integral_constant<int, 6>{}, e, 0);
         put(integral_constant<int, 12>{}, e, +1);
         put(integral_constant<int, 13>{}, e, -1);
-        put(integral_constant<int, 15>{}, decode(r.mm, x, xf, xl), 0);
-        put(integral_constant<int, 16>{}, decode(r.pp, x, xf, xl), 0);
-        put(integral_constant<int, 17>{}, decode(r.mp, x, xf, xl), 0);
-        put(integral_constant<int, 18>{}, decode(r.pm, x, xf, xl), 0);
+        put(integral_constant<int, 15>{}, decode(r.mm(), x, xf, xl), 0);
+        put(integral_constant<int, 16>{}, decode(r.pp(), x, xf, xl), 0);
+        put(integral_constant<int, 17>{}, decode(r.mp(), x, xf, xl), 0);
+        put(integral_constant<int, 18>{}, decode(r.pm(), x, xf, xl), 0);
         if constexpr (WB) wb = walls;
     }
 };
@@ -1026,7 +1025,7 @@ int grid_for(int64_t n) {
 
 TableIdx table_view(const IndexView& v) { return TableIdx{v.table, (uint32_t)v.stride}; }
 BitmapIdx bitmap_view(const IndexView& v) {
-    return BitmapIdx{v.coords, static_cast<const uint4*>(v.rec), (uint32_t)v.nx, (uint32_t)v.ny,
+    return BitmapIdx{v.coords, static_cast<const uint2*>(v.rec), (uint32_t)v.nx, (uint32_t)v.ny,
                      (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by};
 }
 

@@ -25,8 +25,8 @@ struct IndexView {
     int64_t slack;              // elements between a chunk's gather base and the chunk (gather_span)
     const int32_t* table;       // kTable: [18][stride] pull sources, -1 = solid
     const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
-    const void* rec;            // kBitmap: [ny*nz*R] 16-byte row-word records
-    int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = records per row
+    const void* rec;            // kBitmap: [nz][R][ny + 2] 8-byte row-word records
+    int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = words per row
 };
 
 struct StepLaunch {

@@ -1,13 +1,14 @@
 // Brute-force check of the bitmap neighbour index on random periodic images:
 // for every fluid node, the pull sources decoded from its packed coordinate
-// and the nine row records around it (one record per row: fluid bits, the
-// next word's bits, node number before the word, fluid count of the row)
-// must equal the sources of the plain neighbour table -- the node at x - c_i,
-// or -1 where that voxel is solid.  The decode below is a CPU model of the
-// step kernel's: the window of voxels x - 1, x, x + 1 is three bits of the
-// row string starting at padded position x, their node numbers follow from
-// a population count, and the x wrap uses the row's fluid count.  Exit
-// status 0 when every case holds.
+// and the records of its nine rows must equal the sources of the plain
+// neighbour table -- the node at x - c_i, or -1 where that voxel is solid --
+// and every record load must lie inside the record array.  The decode below
+// is a CPU model of the step kernel's: entry (z, y, w) holds the 8-byte
+// records of word w of rows y - 1, y, y + 1 of plane z; a node reads the
+// entries (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 20; the window
+// of voxels x - 1, x, x + 1 is three bits of a record starting at position
+// x mod 20, node numbers follow from a population count, and the x wrap uses
+// the row's fluid count.  Exit status 0 when every case holds.
 #include "lbm_host.hpp"
 #include <cstdio>
 #include <random>
@@ -20,14 +21,14 @@ struct Row3 {
     uint32_t bits;
 };
 Row3 decode(const RowRec& w, int x, int nx) {
-    const uint32_t sh = (uint32_t)x & 31u;
-    const uint64_t pair = ((uint64_t)w.next << 32) | w.bits;
+    const uint32_t sh = (uint32_t)(x % kWordStep);
+    const int64_t count = (int64_t)((w.lo >> 22) | ((w.hi >> 30) << 10));
     Row3 r;
-    r.bits = (uint32_t)(pair >> sh) & 7u;
-    const uint32_t below = (uint32_t)__builtin_popcount(sh == 0 ? 0u : (w.bits & ((1u << sh) - 1u)));
-    r.r0 = (int64_t)w.base + below + (r.bits & 1u);
-    r.rm = r.r0 - 1 + (x == 0 ? w.count : 0);
-    r.rp = r.r0 + ((r.bits >> 1) & 1u) - (x == nx - 1 ? w.count : 0);
+    r.bits = (w.lo >> sh) & 7u;
+    const uint32_t below = (uint32_t)__builtin_popcount(w.lo & ((1u << sh) - 1u));
+    r.r0 = (int64_t)(w.hi & 0x3fffffffu) - 1 + below + (r.bits & 1u);
+    r.rm = r.r0 - 1 + (x == 0 ? count : 0);
+    r.rp = r.r0 + ((r.bits >> 1) & 1u) - (x == nx - 1 ? count : 0);
     return r;
 }
 // source node of the voxel at offset dx (-1, 0, +1) in the decoded row, or -1
@@ -40,7 +41,7 @@ int64_t pick(const Row3& w, int dx) {
 int main() {
     std::mt19937 rng(11);
     int bad = 0, cases = 0;
-    const int edge_nx[] = {1, 2, 3, 29, 30, 31, 32, 33, 34, 62, 63, 64, 65, 66, 95, 96, 97};
+    const int edge_nx[] = {1, 2, 3, 18, 19, 20, 21, 22, 39, 40, 41, 42, 59, 60, 61, 62, 63};
     for (int it = 0; it < 400; ++it) {
         int nx = it < 17 ? edge_nx[it] : 1 + (int)(rng() % 100);
         int ny = 1 + (int)(rng() % 9), nz = 1 + (int)(rng() % 40);
@@ -58,20 +59,31 @@ int main() {
         build_table(g.data(), nx, ny, nz, nf, np, t.data());
         BitmapIndex bm;
         build_bitmap(g.data(), nx, ny, nz, nf, &bm);
-        const int R = bm.recs_per_row;
-        if ((int64_t)bm.rec.size() != (int64_t)ny * nz * R) { ++bad; continue; }
+        const int W = bm.words;
+        const int64_t bytes = (int64_t)bm.rec.size() * 8;
+        if (W != words_per_row(nx) || (int64_t)bm.rec.size() != (int64_t)nz * ny * W * 3) { ++bad; continue; }
         for (int64_t n = 0; n < nf; ++n) {
             const uint32_t c = bm.coords[n];
             const int x = (int)(c & ((1u << cb.bx) - 1u));
             const int y = (int)((c >> cb.bx) & ((1u << cb.by) - 1u));
             const int z = (int)((uint64_t)c >> (cb.bx + cb.by));
-            auto row = [&](int dy, int dz) {
-                const int yy = (y + dy + ny) % ny, zz = (z + dz + nz) % nz;
-                return decode(bm.rec[((int64_t)zz * ny + yy) * R + (x >> 5)], x, nx);
-            };
+            // the kernel's byte offsets: entry (zz, y, w), 16 then 8 bytes
+            RowRec rows[3][3];  // [plane z-1, z, z+1][row y-1, y, y+1]
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int zz = (z + dz + nz) % nz;
+                const int64_t o = (((int64_t)zz * ny + y) * W + x / kWordStep) * 24;
+                if (o < 0 || o + 24 > bytes || o % 8 != 0) {
+                    if (bad < 10) printf("OUT dims %d %d %d node %lld offset %lld bytes %lld\n", nx, ny, nz,
+                                         (long long)n, (long long)o, (long long)bytes);
+                    ++bad;
+                    continue;
+                }
+                for (int k = 0; k < 3; ++k) rows[dz + 1][k] = bm.rec[o / 8 + k];
+            }
             for (int i = 1; i < 19; ++i) {
                 // the source voxel is x - c_i
-                const int64_t got = pick(row(-kC[i][1], -kC[i][2]), -kC[i][0]);
+                const Row3 r = decode(rows[1 - kC[i][2]][1 - kC[i][1]], x, nx);
+                const int64_t got = pick(r, -kC[i][0]);
                 const int64_t want = t[(size_t)(i - 1) * np + n];
                 if (got != want) {
                     if (bad < 10)

@@ -194,11 +194,11 @@ def test_gather_span_bounds_brute_force(tmp_path):
 
 
 def test_bitmap_records_decode_to_neighbour_table(tmp_path):
-    """The bitmap index (packed coordinate per node, one 16-byte record per
-    32 voxels of each row with the next word's bits) decodes, by the step
+    """The bitmap index (packed coordinate per node; per row word, the 8-byte
+    records of rows y - 1, y, y + 1 side by side) decodes, by the step
     kernel's arithmetic modelled on the CPU, to exactly the pull sources of
-    the neighbour table on random periodic images, including row lengths
-    around the 32-voxel word size."""
+    the neighbour table on random periodic images, with every record load in
+    bounds, including row lengths around the 20-voxel word step."""
     import shutil
     import subprocess
     gxx = shutil.which("g++")
