@@ -32,14 +32,14 @@ HBM_PEAK_GBS = 8000.0
 ALG_BYTES = {"f32": 19 * 4 * 2, "f16": 19 * 2 * 2, "bf16": 19 * 2 * 2, "f16r": 20 * 2 * 2}
 # Index bytes per node the design adds: the int32 [18] table; or, for the bitmap,
 # one packed coordinate per node plus the row records read once per step
-# (8 bytes per 20 voxels of a row, stored three times: 24 * ny * nz * words).
+# (8 bytes per 18 voxels of a row, stored three times: 24 * ny * nz * words).
 
 
 def index_bytes(index: str, shape, nf: int) -> float:
     if index == "table":
         return 18 * 4
     nz, ny, nx = shape
-    return 4 + 24 * ny * nz * ((nx + 19) // 20) / nf
+    return 4 + 24 * ny * nz * ((nx + 17) // 18) / nf
 # Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n.
 ADJ_ALG_BYTES = 3 * 19 * 4
 

@@ -91,14 +91,14 @@ extern "C" {
  * LBM_INDEX_TABLE:  int32 [18][n_pad] table of pull-source nodes (-1 = wall),
  *                   72 bytes per fluid node.
  * LBM_INDEX_BITMAP: one packed uint32 voxel coordinate per node plus, for
- *                   every (y, z) row and every 20 voxels of it, an 8-byte
- *                   record (22 fluid bits, the node number before them, the
- *                   row's fluid count), kept side by side with the records of
- *                   rows y - 1 and y + 1 of the same plane; the source node of
- *                   a link is found by a population count.  4 bytes per node
- *                   + 1.2 bytes per voxel.  Needs ceil(log2 nx) + ceil(log2 ny)
- *                   + ceil(log2 nz) <= 32, at most 2^30 - 2 fluid nodes and
- *                   fewer than 2^32 row words (ny nz ceil(nx / 20)). */
+ *                   every (y, z) row and every 18 voxels of it, an 8-byte
+ *                   record (20 fluid bits, the row's fluid count, the node
+ *                   number before them), kept side by side with the records
+ *                   of rows y - 1 and y + 1 of the same plane; the source node
+ *                   of a link is found by a population count.  4 bytes per
+ *                   node + 1.33 bytes per voxel.  Needs ceil(log2 nx) +
+ *                   ceil(log2 ny) + ceil(log2 nz) <= 32, nx <= 4095 and fewer
+ *                   than 2^32 row words (ny nz ceil(nx / 18)). */
 #define LBM_INDEX_TABLE 0
 #define LBM_INDEX_BITMAP 1
 
@@ -139,8 +139,8 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
 /* Host only.  Counts fluid voxels and the device workspace the context
  * needs.  Fails with LBM_ENOFLUID / LBM_ERANGE / LBM_EINVAL as lbm_setup.
  * LBM_ERANGE: 2^31 or more fluid nodes; with the bitmap index, packed
- * coordinates over 32 bits, more than 2^30 - 2 fluid nodes or 2^32 row words
- * or more; or the populations gathered around one 256-node chunk
+ * coordinates over 32 bits, nx above 4095 or 2^32 row words or more; or the
+ * populations gathered around one 256-node chunk
  * spanning 4 GiB or more in the chosen storage (three 16-plane z-tiles of
  * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16, 40 for F16R). */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,

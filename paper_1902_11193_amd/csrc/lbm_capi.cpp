@@ -342,8 +342,8 @@ int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int sto
     if (nf >= ((int64_t)1 << 31) - 256) return fail(LBM_ERANGE, "more than 2^31 fluid nodes");
     if (index_kind == LBM_INDEX_BITMAP && !lbm::coord_bits(nx, ny, nz).fits())
         return fail(LBM_ERANGE, "packed voxel coordinates need more than 32 bits");
-    if (index_kind == LBM_INDEX_BITMAP && nf > lbm::kBitmapMaxNodes)
-        return fail(LBM_ERANGE, "the bitmap index holds at most 2^30 - 2 fluid nodes");
+    if (index_kind == LBM_INDEX_BITMAP && nx > lbm::kBitmapMaxNx)
+        return fail(LBM_ERANGE, "the bitmap index holds rows of at most 4095 voxels");
     if (index_kind == LBM_INDEX_BITMAP && (int64_t)ny * nz * lbm::words_per_row(nx) >= ((int64_t)1 << 32))
         return fail(LBM_ERANGE, "the bitmap index holds fewer than 2^32 row words");
     e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, slots(storage)), storage);

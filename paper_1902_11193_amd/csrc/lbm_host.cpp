@@ -261,7 +261,7 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                         if (q < nx + 2 && pad[q]) bits |= 1u << b;
                     }
                     const int64_t base = rowstart + before - (w == 0 ? pad[0] : 0);
-                    const RowRec rr{bits | (count & 0x3ffu) << 22, (uint32_t)(base + 1) | (count >> 10) << 30};
+                    const RowRec rr{bits | count << 20, (int32_t)base};
                     // this row is row y of its own triple, row y + 1 of row
                     // y - 1's and row y - 1 of row y + 1's (periodic in y; with
                     // ny <= 2 one triple takes it in two or three slots)

@@ -79,25 +79,24 @@ void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_
 // Bitmap index.  Every (y, z) row of the image is a padded bit string of
 // nx + 2 positions: position x + 1 holds voxel x, position 0 repeats voxel
 // nx - 1 and position nx + 1 repeats voxel 0 (the periodic wrap).  Word w of a
-// row covers positions kWordStep w .. kWordStep w + 21: consecutive words
+// row covers positions kWordStep w .. kWordStep w + 19: consecutive words
 // overlap by two positions, so the window x .. x + 2 (voxels x - 1, x, x + 1)
-// of voxel x lies inside word x / kWordStep.  A word's 8-byte record packs its
-// 22 bits, the row's fluid count and one plus the node number counting real
-// voxels before the word (minus the left pad bit on word 0).  For every row
+// of voxel x lies inside word x / kWordStep.  A word's 8-byte record holds its
+// 20 bits with the row's fluid count above them, and the node number counting
+// real voxels before the word (minus the left pad bit on word 0).  For every row
 // (y, z) and word w the array holds the records of rows y - 1, y, y + 1
 // (periodic in y) of plane z side by side, 24 bytes, stored by (z, y, w): a
 // node reads its nine rows with one 16-byte and one 8-byte load per plane,
 // and the nodes of a row read consecutive bytes.  Each node also keeps its
 // packed voxel coordinate.
-constexpr int kWordStep = 20;
+constexpr int kWordStep = 18;
 struct RowRec {
-    uint32_t lo;  // bits 0..21: the word's positions; bits 22..31: count & 0x3ff
-    uint32_t hi;  // bits 0..29: base + 1; bits 30..31: count >> 10
+    uint32_t lo;  // bits 0..19: the word's positions; bits 20..31: the row's fluid count
+    int32_t base;
 };
 static_assert(sizeof(RowRec) == 8, "RowRec is one 8-byte record");
 inline int words_per_row(int nx) { return (nx - 1) / kWordStep + 1; }
-// largest fluid-node count whose record bases fit their 30 bits
-constexpr int64_t kBitmapMaxNodes = ((int64_t)1 << 30) - 2;
+constexpr int kBitmapMaxNx = 4095;  // the row count has 12 bits
 struct BitmapIndex {
     int words = 0;  // records per row
     CoordBits bits{};

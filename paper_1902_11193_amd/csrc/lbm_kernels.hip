@@ -216,12 +216,18 @@ struct TableIdx {
 };
 
 // Row-word records of the padded bit strings built on the host: word w of a
-// row covers padded positions 20 w .. 20 w + 21 (position x + 1 is voxel x,
+// row covers padded positions 18 w .. 18 w + 19 (position x + 1 is voxel x,
 // the two ends repeat the opposite voxel: periodic x), so the window of voxel
-// x lies in word x / 20.  A record is 8 bytes {22 bits | count low 10 bits,
-// base + 1 | count high 2 bits}; entry (z, y, w) holds the records of rows
-// y - 1, y, y + 1 of plane z, 24 bytes: one 16-byte and one 8-byte load.
-constexpr uint32_t kWordStep = 20;
+// x lies in word x / 18.  A record is 8 bytes {20 bits | row count << 20,
+// base}; entry (z, y, w) holds the records of rows y - 1, y, y + 1 of plane
+// z, 24 bytes: one 16-byte and one 8-byte load.
+constexpr uint32_t kWordStep = 18;
+// (a & mask) | (b & ~mask) in one instruction
+__device__ __forceinline__ uint32_t bit_select(uint32_t mask, uint32_t a, uint32_t b) {
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(mask), "v"(a), "v"(b));
+    return r;
+}
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
     const uint2* __restrict__ rec;
@@ -233,13 +239,13 @@ struct BitmapIdx {
         uint32_t bits;
     };
     __device__ __forceinline__ Row3 decode(uint2 rec8, uint32_t x, bool x_first, bool x_last) const {
-        const uint32_t lo = rec8.x, hi = rec8.y;
+        const uint32_t lo = rec8.x;
         const uint32_t sh = x - (x / kWordStep) * kWordStep;
-        const int32_t count = (int32_t)((lo >> 22) | ((hi >> 30) << 10));
+        const int32_t count = (int32_t)(lo >> 20);
         Row3 r;
         r.bits = __builtin_amdgcn_ubfe(lo, sh, 3u);   // padded positions x..x+2
         const int32_t below = (int32_t)__popc(__builtin_amdgcn_ubfe(lo, 0u, sh));
-        r.r0 = (int32_t)(hi & 0x3fffffffu) - 1 + below + (int32_t)(r.bits & 1u);
+        r.r0 = (int32_t)rec8.y + below + (int32_t)(r.bits & 1u);
         r.rm = r.r0 - 1 + (x_first ? count : 0);
         r.rp = r.r0 + (int32_t)((r.bits >> 1) & 1u) - (x_last ? count : 0);
         return r;
@@ -341,7 +347,7 @@ struct BitmapIdx {
             const uint32_t fluid = (uint32_t)__builtin_amdgcn_sbfe((int32_t)w.bits, (uint32_t)(which + 1), 1u);
             const uint32_t pulled = node_elem<S>(v) * sz + (kb + (uint32_t)i * kThreads * sz);
             const uint32_t own = ekb + (uint32_t)opp(i) * kThreads * sz;
-            off[i] = (pulled & fluid) | (own & ~fluid);
+            off[i] = bit_select(fluid, pulled, own);
             if constexpr (WB) walls |= ~fluid & (1u << i);
         };
         using std::integral_constant;

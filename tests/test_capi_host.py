@@ -145,6 +145,23 @@ def test_workspace_query_counts_and_errors():
     assert L.lbm_workspace_query(None, 2, 2, 2, 0, 0, ctypes.byref(nbytes), ctypes.byref(n)) == P.LBM_EINVAL
 
 
+def test_bitmap_row_length_limit():
+    """The bitmap's row records keep the row's fluid count in 12 bits: rows of
+    up to 4095 voxels are accepted, longer ones are refused (LBM_ERANGE) and
+    the table index takes them."""
+    for nx, ok in ((4095, True), (4096, False)):
+        m = np.zeros((1, 1, nx), np.uint8)
+        if ok:
+            nb, nf = P.lbm_workspace_query(m, "f16", "bitmap")
+            assert nf == nx and nb > 0
+        else:
+            with pytest.raises(P.LbmError) as e:
+                P.lbm_workspace_query(m, "f16", "bitmap")
+            assert e.value.code == P.LBM_ERANGE
+            assert b"4095" in P.lib().lbm_last_error()
+        assert P.lbm_workspace_query(m, "f16", "table")[1] == nx
+
+
 def _setup_rc(mask, tau=1.0, Lam=0.1875, rset=5, g=(1e-6, 0, 0), storage=0, index=1, ws=None, nbytes=None):
     """Call lbm_setup with a fake (never dereferenced) workspace; validation fails first."""
     L = P.lib()
@@ -198,7 +215,7 @@ def test_bitmap_records_decode_to_neighbour_table(tmp_path):
     records of rows y - 1, y, y + 1 side by side) decodes, by the step
     kernel's arithmetic modelled on the CPU, to exactly the pull sources of
     the neighbour table on random periodic images, with every record load in
-    bounds, including row lengths around the 20-voxel word step."""
+    bounds, including row lengths around the 18-voxel word step."""
     import shutil
     import subprocess
     gxx = shutil.which("g++")

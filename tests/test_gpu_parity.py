@@ -61,9 +61,14 @@ def test_populations_match_oracle(name, make, index):
             assert np.allclose(ug, uo, rtol=0, atol=1e-6 * np.abs(uo).max()), (n, ug, uo)
 
 
-def test_table_and_bitmap_bitwise_equal():
-    mask = random_mask((9, 10, 70), 0.3, 5)
-    banner("table vs bitmap 9x10x70")
+@pytest.mark.parametrize("shape,solid", [((9, 10, 70), 0.3), ((5, 3, 18), 0.3), ((4, 7, 19), 0.2),
+                                         ((6, 4, 37), 0.4), ((3, 1, 36), 0.1), ((3, 2, 4095), 0.05)])
+def test_table_and_bitmap_bitwise_equal(shape, solid):
+    """The bitmap index reaches the same pull sources as the table: states and
+    histories agree bit for bit, for row lengths around the bitmap's 18-voxel
+    word step, a single-row-per-plane image and the longest rows it holds."""
+    mask = random_mask(shape, solid, 5)
+    banner(f"table vs bitmap {shape}")
     states = []
     for index in ("table", "bitmap"):
         s = P.Solver(mask, 0.9, 1 / 12, "E", G, "f32", index)
