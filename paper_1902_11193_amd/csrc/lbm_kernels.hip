@@ -272,6 +272,12 @@ struct BitmapIdx {
         __device__ __forceinline__ uint2 mp() const { return make_uint2(a[2].x, a[2].y); }  // y - 1, z + 1
         __device__ __forceinline__ uint2 pp() const { return b[2]; }                        // y + 1, z + 1
     };
+    // two records (16 bytes) at an 8-byte aligned address
+    static __device__ __forceinline__ uint4 load16(const uint2* p) {
+        typedef uint32_t V4 __attribute__((ext_vector_type(4), aligned(8)));
+        const V4 v = *reinterpret_cast<const V4*>(p);
+        return make_uint4(v.x, v.y, v.z, v.w);
+    }
     // issue the six record loads of the node with packed coordinate c
     __device__ __forceinline__ void load(uint32_t, Pre c, Raw& r) const {
         const uint32_t x = c & ((1u << bx) - 1u);
@@ -285,11 +291,11 @@ struct BitmapIdx {
         const uint2* p0 = rec + (uint64_t)e * 3u;
         const uint2* pp = rec + (uint64_t)ep * 3u;
         __builtin_amdgcn_sched_barrier(0);
-        r.a[0] = *reinterpret_cast<const uint4*>(pm);
+        r.a[0] = load16(pm);
         r.b[0] = pm[2];
-        r.a[1] = *reinterpret_cast<const uint4*>(p0);
+        r.a[1] = load16(p0);
         r.b[1] = p0[2];
-        r.a[2] = *reinterpret_cast<const uint4*>(pp);
+        r.a[2] = load16(pp);
         r.b[2] = pp[2];
     }
     // pull sources s[i] (node number or -1) from the decoded rows
