@@ -25,7 +25,7 @@ struct IndexView {
     int64_t slack;              // elements between a chunk's gather base and the chunk (gather_span)
     const int32_t* table;       // kTable: [18][stride] pull sources, -1 = solid
     const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
-    const void* rec;            // kBitmap: [nz][R][ny + 2] 8-byte row-word records
+    const void* rec;            // kBitmap: [nz][ny][R][3] 8-byte records (rows y - 1, y, y + 1)
     int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = words per row
 };
 
