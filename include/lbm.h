@@ -212,6 +212,10 @@ int lbm_permeability(lbm_ctx* ctx, double k[3]);
  * (FP64); exact mass conservation keeps it at rounding level. */
 int lbm_mass_deviation(lbm_ctx* ctx, double* dm);
 
+/* Total mass sum_fluid rho = n_fluid rho0 + lbm_mass_deviation (rho0 = 1),
+ * at the last step (n_fluid before the first).  Synchronises the stream. */
+int lbm_mass(lbm_ctx* ctx, double* m);
+
 /* Per-step mean velocities of the last `count` steps (count <= 1024 and
  * <= steps done), oldest first, into u[count][3] (host).  Synchronises. */
 int lbm_history(lbm_ctx* ctx, int count, double* u);

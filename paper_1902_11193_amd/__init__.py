@@ -41,6 +41,7 @@ SIGNATURES = {
     "lbm_mean_velocity": (c_int, [c_void_p, POINTER(c_double)]),
     "lbm_permeability": (c_int, [c_void_p, POINTER(c_double)]),
     "lbm_mass_deviation": (c_int, [c_void_p, POINTER(c_double)]),
+    "lbm_mass": (c_int, [c_void_p, POINTER(c_double)]),
     "lbm_history": (c_int, [c_void_p, c_int, POINTER(c_double)]),
     "lbm_run_to_steady": (c_int, [c_void_p, c_double, c_int, c_int, POINTER(c_int), POINTER(c_double), POINTER(c_int)]),
     "lbm_get_state": (c_int, [c_void_p, POINTER(c_double)]),
@@ -224,6 +225,12 @@ class Solver:
         k = np.zeros(3)
         _check(lib().lbm_permeability(self._ctx, _dptr(k, c_double)))
         return k
+
+    def mass(self) -> float:
+        """Total mass sum_fluid rho at the last step."""
+        d = c_double()
+        _check(lib().lbm_mass(self._ctx, byref(d)))
+        return d.value
 
     def mass_deviation(self) -> float:
         d = c_double(0)

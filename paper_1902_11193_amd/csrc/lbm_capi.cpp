@@ -574,6 +574,15 @@ int lbm_permeability(lbm_ctx* c, double k[3]) {
     return LBM_OK;
 }
 
+int lbm_mass(lbm_ctx* c, double* m) {
+    if (!c || !m) return fail(LBM_EINVAL, "NULL argument");
+    double dm = 0.0;
+    const int rc = lbm_mass_deviation(c, &dm);
+    if (rc) return rc;
+    *m = (double)c->nf + dm;  // rho0 = 1
+    return LBM_OK;
+}
+
 int lbm_mass_deviation(lbm_ctx* c, double* dm) {
     if (!c || !dm) return fail(LBM_EINVAL, "NULL argument");
     if (c->steps == 0) {

@@ -145,6 +145,8 @@ def test_mass_is_conserved():
     dm = s.mass_deviation()
     # FP32 rounding random walk: per node and step ~1e-11 on deviations ~1e-4
     assert abs(dm) < 1e-6 * s.n_fluid * 1e-4
+    # total mass: n_fluid rho0 plus that deviation
+    assert s.mass() == s.n_fluid + dm
 
 
 def test_sc_sphere_permeability_matches_oracle_golden():
