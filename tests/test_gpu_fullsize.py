@@ -43,10 +43,14 @@ def _oracle_step(f_src, sample, t, fo_of):
     return want
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16r", "f16", "bf16"])
-def test_sampled_step_grf_1024(rock, storage):
-    banner(f"grf_1024 sampled step {storage}")
+@pytest.mark.parametrize("storage,collision", [("f32", "mrt"), ("f16r", "mrt"), ("f16", "mrt"), ("bf16", "mrt"),
+                                               ("f32", "trt")])
+def test_sampled_step_grf_1024(rock, storage, collision):
+    """(Set E is a two-rate set, so the link-wise TRT kernel computes the
+    oracle's moment-space collision too.)"""
+    banner(f"grf_1024 sampled step {storage} {collision}")
     s = P.Solver(rock, 1.0, 3 / 16, "E", (G, 0, 0), storage, "bitmap")
+    s.set_collision(collision)
     nf = s.n_fluid
     rng = np.random.default_rng(5)
     sample = np.sort(rng.choice(nf, 4096, replace=False))
@@ -59,7 +63,8 @@ def test_sampled_step_grf_1024(rock, storage):
     s.step(1)
     got = s.get_state_nodes(sample)
     want = _oracle_step(f20, sample, t, fo_of)
-    print(f"[fullsize] {storage}: max error / deviation scale {deviation_error(got, want):.3e}", flush=True)
+    print(f"[fullsize] {storage} {collision}: max error / deviation scale {deviation_error(got, want):.3e}",
+          flush=True)
     if storage == "f32":
         assert deviation_error(got, want) < 2e-6
     elif storage == "f16r":
