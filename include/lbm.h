@@ -7,7 +7,7 @@
  * equation (Sec. 2, Eq. LBE) with the MRT collision of Sec. 2.1.1
  * (Eqs. MRT Collision, MRT Equi, MRT params), Guo body forcing
  * (Eqs. MRT-LBE, Guo_Forcing), halfway bounce-back at solid voxels in a
- * periodic box driven by a uniform body force (Sec. 2.2), and the Darcy
+ * periodic box driven by a uniform body force (Sec. 2.3), and the Darcy
  * permeability k_j = nu <u_j> / g_j (Sec. 3, Eq. perm_calc) with the
  * steady-state test of Eq. convergence.
  *
@@ -64,7 +64,7 @@ extern "C" {
 #define LBM_ENAN (-5)       /* non-finite mean velocity or mass: the run diverged or overflowed */
 #define LBM_ERANGE (-6)     /* image too large for the index or gather layout */
 
-/* Relaxation-rate sets of Table 2 (Sec. 2.1.3). */
+/* Relaxation-rate sets of Table 2 (Sec. 2.2). */
 #define LBM_SRT 0
 #define LBM_SET_A 1
 #define LBM_SET_B 2
@@ -116,7 +116,7 @@ extern "C" {
  * LBM_WALL_HALFWAY: the wall midway between a fluid and a solid voxel; a
  *                   population sent into it returns at the next step.  The
  *                   default, and the scheme every other statement here uses.
- * LBM_WALL_FULLWAY: the paper's full-way bounce-back (Sec. 2.2): the
+ * LBM_WALL_FULLWAY: the paper's full-way bounce-back (Sec. 2.3): the
  *                   population travels to the solid voxel, turns there at the
  *                   next collision and returns one step later than halfway.
  *                   The steady state at fluid nodes is the same. */
@@ -146,7 +146,7 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
 
-/* Host only.  Non-periodic image stacks (Sec. 2.2, the paper's sphere-pack
+/* Host only.  Non-periodic image stacks (Sec. 2.3, the paper's sphere-pack
  * setup): `pad` fluid-only layers are added before and after the image along
  * x, the driven axis, and with mirror_y / mirror_z the image is reflected
  * across its y / z faces.  In the periodic box this gives, the reflected faces
@@ -184,24 +184,39 @@ int lbm_node_order(const uint8_t* geometry, int nx, int ny, int nz, int64_t* vox
 int lbm_neighbor_table(const uint8_t* geometry, int nx, int ny, int nz, int32_t* table,
                        int64_t n_fluid);
 
-/* Builds the context: copies and compacts the geometry (borrowed for the
- * call only), computes the rates, uploads the index to `workspace` and sets
- * the state to rest.  g[3] is the body-force acceleration (lattice units);
- * F = rho0 g acts on every fluid node.  `hip_stream` is a hipStream_t (NULL =
+/* The problem of Sec. 2 and Sec. 3 (Eq. LBE, with Eq. MRT-LBE for the
+ * forced MRT collision): a segmented image, the relaxation time tau (the
+ * viscosity nu = (tau - 1/2)/3), a relaxation set of Table 2 with the magic
+ * parameter Lambda of Eq. Magic param (Set E), and a body force driving the
+ * flow (Sec. 2.3).  Builds the context: copies and compacts the geometry
+ * (borrowed for the call only; the solid voxels carry no work, Sec. 3),
+ * computes the rates, uploads the index to `workspace` and sets the state to
+ * rest.  g[3] is the body-force acceleration (lattice units); F = rho0 g acts
+ * on every fluid node.  Errors: LBM_EINVAL (NULL ctx, geometry or g, bad
+ * extents, tau <= 1/2, a set outside 0..5, Lambda <= 0 for Set E, a rate
+ * outside (0, 2), non-finite g), LBM_ENOFLUID, LBM_ERANGE,
+ * LBM_EWORKSPACE (NULL, not 256-byte aligned, smaller than
+ * lbm_workspace_query's bytes), LBM_EHIP; *ctx is NULL on error.  `hip_stream` is a hipStream_t (NULL =
  * the default stream).  Returns the context in *ctx (owned by the caller,
  * freed with lbm_destroy).  Synchronises the stream before returning. */
 int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
               double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
               void* workspace, size_t workspace_bytes, void* hip_stream);
 
-/* Advances n >= 0 time steps (asynchronous on the context's stream). */
+/* Advances n >= 0 time steps of Eq. LBE (Sec. 2): per step every fluid node
+ * pulls f_i from x - c_i (halfway bounce-back where that voxel is solid),
+ * collides in moment space (Eq. MRT-LBE with the equilibria of Eq. MRT Equi
+ * and Guo's source, Eq. Guo_Forcing) and stores the result; the same launch
+ * sums the node velocities for <u>_n.  Asynchronous on the context's stream.
+ * LBM_EINVAL for n < 0, LBM_EHIP if a launch fails. */
 int lbm_step(lbm_ctx* ctx, int n);
 
 /* Steps taken since setup (or since the last lbm_set_state). */
 int64_t lbm_steps_done(const lbm_ctx* ctx);
 
-/* Mean velocity <u>_n of the last step (FP64).  Synchronises the stream.
- * LBM_ENAN if it is not finite.  Before the first step: zeros. */
+/* Mean velocity <u>_n of the last step (FP64), the volume average of
+ * Eq. perm_calc.  Synchronises the stream.  LBM_ENAN if it is not finite.
+ * Before the first step: zeros. */
 int lbm_mean_velocity(lbm_ctx* ctx, double u[3]);
 
 /* k_j = nu <u_j>_n / g_j with nu = (tau - 1/2)/3 (Eq. perm_calc); NaN where
@@ -209,15 +224,18 @@ int lbm_mean_velocity(lbm_ctx* ctx, double u[3]);
 int lbm_permeability(lbm_ctx* ctx, double k[3]);
 
 /* Sum over fluid nodes of the density deviation rho - rho0 at the last step
- * (FP64); exact mass conservation keeps it at rounding level. */
+ * (FP64); the collision leaves rho unrelaxed (s_0 = 0 in Table 2) and the
+ * stream with bounce-back moves populations without loss, so it stays at
+ * rounding level. */
 int lbm_mass_deviation(lbm_ctx* ctx, double* dm);
 
 /* Total mass sum_fluid rho = n_fluid rho0 + lbm_mass_deviation (rho0 = 1),
  * at the last step (n_fluid before the first).  Synchronises the stream. */
 int lbm_mass(lbm_ctx* ctx, double* m);
 
-/* Per-step mean velocities of the last `count` steps (count <= 1024 and
- * <= steps done), oldest first, into u[count][3] (host).  Synchronises. */
+/* Per-step mean velocities (Eq. perm_calc) of the last `count` steps (count
+ * <= 1024 and <= steps done), oldest first, into u[count][3] (host): the
+ * history the test of Eq. convergence reads.  Synchronises. */
 int lbm_history(lbm_ctx* ctx, int count, double* u);
 
 /* Steps in chunks of `check_every` until the per-step relative change of
@@ -236,8 +254,9 @@ int lbm_run_to_steady(lbm_ctx* ctx, double eps, int check_every, int max_steps, 
  * for sampled checks of images too large to copy whole.  Synchronises. */
 int lbm_get_state_nodes(lbm_ctx* ctx, const int64_t* nodes, int64_t count, double* f);
 
-/* Host copies of the state: full populations f_i = w_i rho0 + deviation in
- * FP64, layout [19][n_fluid] (host memory owned by the caller).
+/* Host copies of the state, the post-collision populations of Eq. LBE:
+ * full populations f_i = w_i rho0 + deviation in FP64, layout
+ * [19][n_fluid] (host memory owned by the caller).
  * lbm_set_state also resets the step count and the mean-velocity history.
  * Synchronise the stream. */
 int lbm_get_state(lbm_ctx* ctx, double* f);
@@ -246,7 +265,8 @@ int lbm_set_state(lbm_ctx* ctx, const double* f);
 /* Linear voxel id (x + nx (y + ny z)) of every fluid node, host int64 [n_fluid]. */
 int lbm_fluid_index(lbm_ctx* ctx, int64_t* voxel);
 
-/* Optional per-node body force: a device FP32 array [3][n_fluid] of
+/* Optional per-node body force, the F of Eq. MRT-LBE and Eq. Guo_Forcing
+ * varying from node to node: a device FP32 array [3][n_fluid] of
  * accelerations owned by the caller, read by every later step (it must stay
  * alive and unchanged until replaced).  NULL returns to the uniform g of
  * lbm_setup.  k keeps dividing by the g of lbm_setup. */
@@ -271,7 +291,7 @@ int lbm_set_collision(lbm_ctx* ctx, int collision);
 int lbm_wall_workspace_query(lbm_ctx* ctx, size_t* bytes);
 int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes);
 
-/* Host only.  Pressure-driven flow (Sec. 2.2, 3.1): with enable != 0 the box
+/* Host only.  Pressure-driven flow (Sec. 2.3, 3.1): with enable != 0 the box
  * is no longer periodic in x; the fluid nodes of the planes x = 0 and
  * x = nx - 1 get Zou-He pressure boundaries at densities rho_in and rho_out
  * (rho0 = 1): the populations arriving from outside the image are rebuilt

@@ -26,11 +26,11 @@ Models for Micro-tomographic Pore-spaces", arXiv:1902.11193):
 * Guo body forcing in MRT (Eq. MRT-LBE, Eq. Guo_Forcing and the
   post-collision moments that follow it): the source F_i is built from the
   shifted velocity u = (sum_i f_i c_i + F/2)/rho0 and projected with M;
-* halfway bounce-back at solid voxels (Sec. 2.2, the wall midway between a
-  fluid and a solid voxel) in a periodic box with a body force (Sec. 2.2);
+* halfway bounce-back at solid voxels (Sec. 2.3, the wall midway between a
+  fluid and a solid voxel) in a periodic box with a body force (Sec. 2.3);
   as options, the paper's full-way bounce-back and symmetry (mirror) planes
-  on the box faces (Sec. 2.2), and Zou-He pressure boundaries on the x faces
-  with k from the pressure drop (Sec. 2.2, 3.1, Eq. perm_calc);
+  on the box faces (Sec. 2.3), and Zou-He pressure boundaries on the x faces
+  with k from the pressure drop (Sec. 2.3, 3.1, Eq. perm_calc);
 * the two-relaxation-time collision in velocity space (Sec. 2.1.2), the
   link-wise form of the MRT collision for two-rate sets (SRT, B, E);
 * the Darcy permeability k_j = nu <u_j> / g_j from the volume-averaged
@@ -274,14 +274,14 @@ def stream_general(fh: torch.Tensor, solid: torch.Tensor, lat: Lattice, symmetri
     options the periodic ``stream`` lacks:
 
     * ``symmetric[a]``: the box faces normal to axis a are symmetry (mirror)
-      planes, half a voxel outside the first and last layers (Sec. 2.2): a pull
+      planes, half a voxel outside the first and last layers (Sec. 2.3): a pull
       that leaves the box through such a face takes, from the voxel reached by
       the tangential part of the step alone, the population of the velocity
       mirrored in that axis;
     * ``fh_wall``: the state the bounce-back reads, fh itself for halfway
       bounce-back, or the state one step older for full-way bounce-back, where
       a population reaches the wall voxel, turns there at the next collision
-      and comes back one step later than with the wall midway (Sec. 2.2).
+      and comes back one step later than with the wall midway (Sec. 2.3).
 
     Halfway bounce-back applies when the (mirrored) source voxel is solid.
     """
@@ -311,7 +311,7 @@ def stream_general(fh: torch.Tensor, solid: torch.Tensor, lat: Lattice, symmetri
 
 
 def zou_he_pressure(f: torch.Tensor, lat: Lattice, rho_in: float, rho_out: float) -> torch.Tensor:
-    """Zou-He pressure boundaries on the x faces (Sec. 2.2, Sec. 3.1): at the
+    """Zou-He pressure boundaries on the x faces (Sec. 2.3, Sec. 3.1): at the
     fluid voxels of the plane x = 0 the five populations with c_x = +1, and of
     x = nx - 1 those with c_x = -1, come from outside the image; they are
     rebuilt so that the density is the prescribed one, the transverse velocity
@@ -434,7 +434,7 @@ class Problem:
         # is then not periodic in x and k follows from the pressure drop
         self.pressure = None if pressure is None else (float(pressure[0]), float(pressure[1]))
         # symmetry planes on the faces normal to the named axes (subset of "xyz"),
-        # and full-way instead of halfway bounce-back (Sec. 2.2)
+        # and full-way instead of halfway bounce-back (Sec. 2.3)
         self.symmetric = tuple(a in symmetric for a in "xyz")
         self.fullway = bool(fullway)
         self.general = any(self.symmetric) or self.fullway or self.pressure is not None

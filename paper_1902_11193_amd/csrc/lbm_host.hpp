@@ -105,7 +105,7 @@ struct BitmapIndex {
 };
 void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out);
 
-// Non-periodic image stacks (Sec. 2.2): `pad` fluid-only layers before and
+// Non-periodic image stacks (Sec. 2.3): `pad` fluid-only layers before and
 // after the image along x, then the image reflected across its y and/or z
 // faces, so that those faces become symmetry (mirror) planes of the periodic
 // box.  out is [nz'][ny'][nx'] with nx' = nx + 2 pad, ny' = ny (x2 when

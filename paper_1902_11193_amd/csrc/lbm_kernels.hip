@@ -5,7 +5,7 @@
 // (Sec. 2, Eq. LBE), MRT collision in moment space (Sec. 2.1.1, Eqs. MRT
 // Collision, MRT Equi, MRT params), Guo forcing (Eqs. MRT-LBE,
 // Guo_Forcing), halfway bounce-back and a periodic body-force-driven box
-// (Sec. 2.2), volume-averaged velocity for Darcy's law (Eq. perm_calc).
+// (Sec. 2.3), volume-averaged velocity for Darcy's law (Eq. perm_calc).
 //
 // Design for CDNA4: every fluid node is one lane of a wave64; populations are
 // stored chunk by chunk, the 256 nodes of a chunk (one block's share of a
@@ -501,7 +501,7 @@ __device__ __forceinline__ Mom collide_increment(const Mom& m, float jx, float j
 }
 
 // ------------------------------------------------------------------ Zou-He
-// Pressure boundaries on the x faces (Sec. 2.2, 3.1).  On the plane x = 0
+// Pressure boundaries on the x faces (Sec. 2.3, 3.1).  On the plane x = 0
 // (side 1) the populations with c_x = +1, on x = nx - 1 (side 2) those with
 // c_x = -1, arrive from outside the image; they are rebuilt from the known
 // ones so that the node has the prescribed density deviation (drho_in /
@@ -663,7 +663,7 @@ k_finalize_ring(const double* __restrict__ partials, int grid, double* __restric
 }
 
 // ------------------------------------------------------------------ step
-// FW: full-way bounce-back (Sec. 2.2).  A population sent into a wall comes
+// FW: full-way bounce-back (Sec. 2.3).  A population sent into a wall comes
 // back one step later than with the halfway wall, so at a wall link the node
 // takes fh_opp(i) of two steps ago.  `wall` keeps, per node and population p,
 // the fh_p this node had one step ago (same layout as a state): at a wall link
@@ -700,7 +700,8 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
     // the populations of node n are gathered, the neighbour index of the next
     // node n1 is resolved and the coordinate of the one after (n2) is
     // fetched, so each iteration waits for memory once.  Node numbers past
-    // the list are clamped to the last node for loads and never stored.
+    // the list are clamped to the last node for loads; what such a lane
+    // stores goes to its own padded slot (below).
     auto node_of = [&](uint32_t cc) { return min(cc * kThreads + threadIdx.x, nf - 1); };
     uint32_t c = lb;
     if (c < chunks) {
@@ -745,7 +746,9 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             }
             float wv[19];
             float* wc = FW ? wall + (size_t)c * kChunkElems : nullptr;
-            const uint32_t own = (n & (kThreads - 1u)) * 4u;
+            // a lane's own slot in chunk c: node c * 256 + lane, or for a lane
+            // past the list a padded slot that no other lane reads or writes
+            const uint32_t own = threadIdx.x * 4u;
             if constexpr (FW) {
                 unroll<18>([&](auto k) {
                     constexpr int i = decltype(k)::value + 1;
@@ -804,17 +807,18 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
                 drho = m.rho;
                 add_back(f, collide_increment(m, jx, jy, jz, Fx, Fy, Fz, r));
             }
-            // Lanes past the list carry n = nf - 1: they recompute that node
-            // from the same inputs and store the same values, so the stores
-            // stay unconditional (no branch for the compiler to sink the
-            // gathers into); only the reduction masks them out.
-            const double live = (c * kThreads + threadIdx.x < nf) ? 1.0 : 0.0;
-            acc[0] += live * (double)jx;
-            acc[1] += live * (double)jy;
-            acc[2] += live * (double)jz;
-            acc[3] += live * (double)drho;
+            // Lanes past the list carry n = nf - 1 for their loads and write
+            // their results to their own padded slots (element lane of the
+            // last chunk), which nothing reads, so the stores stay
+            // unconditional (no branch for the compiler to sink the gathers
+            // into); the reduction leaves them out.
+            const bool live = c * kThreads + threadIdx.x < nf;
+            acc[0] += live ? (double)jx : 0.0;
+            acc[1] += live ? (double)jy : 0.0;
+            acc[2] += live ? (double)jz : 0.0;
+            acc[3] += live ? (double)drho : 0.0;
             T* db = dst + (size_t)c * (S * kThreads);
-            const uint32_t so = (n & (kThreads - 1u)) * (uint32_t)sizeof(T);
+            const uint32_t so = threadIdx.x * (uint32_t)sizeof(T);
             if constexpr (REF) {
                 // the node's new reference: its density deviation, which the
                 // collision conserves, rounded to the stored type

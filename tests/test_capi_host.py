@@ -42,6 +42,18 @@ def test_velocity_order_matches_header_and_pairs():
 
 
 @pytest.mark.parametrize("rset", list(P.SETS))
+@pytest.mark.parametrize("tau_key", ["0.6", "1.3"])
+def test_rates_equal_table2_entries(rset, tau_key):
+    """lbm_rates against Table 2 evaluated by hand (tests/golden/paper_values.json)."""
+    import json
+    from fractions import Fraction
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))["table2_rates"]
+    want = [float(Fraction(v)) for v in gold["rates"][tau_key][rset]]
+    s, _, _ = P.lbm_rates(rset, float(tau_key), float(Fraction(gold["Lambda_E"])))
+    assert np.allclose(s, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("rset", list(P.SETS))
 @pytest.mark.parametrize("tau", [0.6, 1.0, 1.37])
 def test_rates_match_oracle_and_derivatives(rset, tau):
     Lam = 0.21

@@ -1,4 +1,4 @@
-"""GPU parity of the non-periodic image boundaries (Sec. 2.2): full-way
+"""GPU parity of the non-periodic image boundaries (Sec. 2.3): full-way
 bounce-back against the oracle's full-way stream, and the padded / mirrored
 image (lbm_boundary_image) against the oracle's symmetry planes on the
 original image.  FP32 storage, 2e-6 of the deviation scale as in the other
@@ -166,4 +166,46 @@ def test_pressure_mode_errors():
     with pytest.raises(P.LbmError):
         s.adjoint(10, 5)
     s.set_pressure(None)
+    s.close()
+
+
+def test_fullway_last_node_with_many_chunks_per_block():
+    """Full-way bounce-back on an image large enough that every block walks
+    several chunks (waves of a block drift apart), with the last node of the
+    list on a wall link and the lanes past the list filling later waves of the
+    last chunk: they must not touch that node's delay-line or state slots."""
+    mask = random_mask((100, 104, 112), 0.1, 7)
+    order = P.lbm_node_order(mask)
+    nz, ny, nx = mask.shape
+    last = int(order[-1])
+    x, y, z = last % nx, (last // nx) % ny, last // (nx * ny)
+    mask[z, y, (x + 1) % nx] = 1                 # a wall link at the last node
+    # drop fluid voxels from the front of the list until 70 lanes of the last
+    # chunk are live: node nf-1 in wave 1, waves 2 and 3 past the list
+    nf = int(np.count_nonzero(mask == 0))
+    drop = (nf - 70) % 256
+    front = P.lbm_node_order(mask)[:drop]
+    mask.reshape(-1)[front] = 1
+    nf = int(np.count_nonzero(mask == 0))
+    assert nf % 256 == 70 and int(P.lbm_node_order(mask)[-1]) == last
+    banner(f"fullway many chunks per block, nf={nf}")
+    s = P.Solver(mask, 0.9, 3 / 16, "E", G, "f32", "bitmap")
+    s.set_wall("fullway")
+    f0 = random_state(s.n_fluid, 9)
+    s.set_state(f0)
+    f0 = s.get_state()
+    p = O.Problem(mask, 0.9, 3 / 16, "E", G, fullway=True)
+    d0 = dense_from_lib(p, f0)
+    fh = torch.stack([d0, d0.clone()])
+    done = 0
+    for n in (1, 2, 50):
+        s.step(n - done)
+        for _ in range(n - done):
+            fh, _ = p.step(fh)
+        done = n
+        got, ref = s.get_state(), lib_from_dense(p, fh[0])
+        err_last = deviation_error(got[:, -1:], ref[:, -1:])
+        err = deviation_error(got, ref)
+        print(f"step {n}: last node {err_last:.2e}, all nodes {err:.2e}", flush=True)
+        assert err_last < 2e-6 and err < 2e-6, (n, err_last, err)
     s.close()

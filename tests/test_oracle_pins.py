@@ -124,6 +124,22 @@ def test_rate_sets_magic_products(tau):
     assert abs(lp * _lam(sA[4]) - 3 / 16) < 1e-14   # A shares B's odd rates
 
 
+def _table2(tau_key, rset):
+    from fractions import Fraction
+    return [float(Fraction(v)) for v in GOLD["table2_rates"]["rates"][tau_key][rset]]
+
+
+@pytest.mark.parametrize("tau_key", ["0.6", "1.3"])
+@pytest.mark.parametrize("rset", ["SRT", "A", "B", "C", "D", "E"])
+def test_rates_equal_table2_entries(tau_key, rset):
+    """All 19 rates of every set against Table 2 evaluated by hand (exact
+    fractions, tests/golden/paper_values.json): pins every entry, Set A's
+    even-sector rates s_e, s_eps, s_pi included."""
+    lam = float(__import__("fractions").Fraction(GOLD["table2_rates"]["Lambda_E"]))
+    got = O.rates(rset, float(tau_key), lam if rset == "E" else None).numpy()
+    assert np.allclose(got, _table2(tau_key, rset), rtol=0, atol=1e-15)
+
+
 @pytest.mark.parametrize("tau", [0.6, 1.0, 1.3])
 def test_rate_sets_structure(tau):
     s = 1 / tau
@@ -265,7 +281,7 @@ def _slit_k(H, Ly, Leff):
 def test_slit_exact_profile_linear(rset, tau, Lam):
     """Plane Poiseuille flow between bounce-back walls: parabola plus a
     Lambda-dependent slip, exact at steady state; Lambda = 3/16 puts the
-    no-slip wall exactly midway (Sec. 2.1.3, Set E)."""
+    no-slip wall exactly midway (Sec. 2.2, Set E)."""
     H, Ly = 8, 10
     m = slit(1, Ly, 1, H)
     g = 1e-6
@@ -413,7 +429,7 @@ def test_trt_slit_exact_profile():
     assert np.abs(u[0].numpy() / want - 1).max() < 1e-8
 
 
-# ---------------------------------------------------------------- symmetry planes, full-way bounce-back (Sec. 2.2)
+# ---------------------------------------------------------------- symmetry planes, full-way bounce-back (Sec. 2.3)
 def _mirror_yz(m):
     mm = np.concatenate([m, m[:, ::-1, :]], axis=1)
     return np.concatenate([mm, mm[::-1]], axis=0)
@@ -490,7 +506,7 @@ def test_fullway_steady_state_equals_halfway():
     assert abs(ks[1] / ks[0] - 1) < 1e-9
 
 
-# ---------------------------------------------------------------- Zou-He pressure boundaries (Sec. 2.2, 3.1)
+# ---------------------------------------------------------------- Zou-He pressure boundaries (Sec. 2.3, 3.1)
 def test_zou_he_sets_density_and_zero_transverse_velocity():
     lat = O.Lattice.make()
     g = torch.Generator().manual_seed(6)
