@@ -862,7 +862,7 @@ int lbm_set_storage_exponent(lbm_ctx* c, int e) {
 // ---------------------------------------------------------------- adjoint
 namespace {
 struct AdjLayout {
-    size_t snaps, seg, adjA, adjB, part6, scratch4, out6, total;
+    size_t snaps, seg, adjA, adjB, acc, part6, scratch4, out6, total;
     int nsnap;
 };
 AdjLayout adj_layout(const lbm_ctx* c, int n_steps, int K) {
@@ -878,6 +878,8 @@ AdjLayout adj_layout(const lbm_ctx* c, int n_steps, int K) {
     off += state;
     a.adjB = off;
     off += state;
+    a.acc = off;  // FP32 body-force sensitivity of one segment, [3][np]
+    off += align256((size_t)3 * c->np * 4);
     a.part6 = off;
     off += align256((size_t)kMaxGrid * 6 * 8);
     a.scratch4 = off;
@@ -946,7 +948,8 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
     al.rates = rates_f(c->rates);
     for (int a = 0; a < 3; ++a) al.F[a] = (float)c->g[a];
     al.field = c->field;
-    al.dk_dF = dk_dg;
+    al.dk_acc = (float*)(ws + A.acc);
+    al.acc_stride = c->np;
     al.grid = c->grid;
     al.partials = part6;
     const int nrev = N - 1;  // reverse steps n = N-1 .. 1
@@ -962,9 +965,12 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
             al.adj_in = a_in;
             al.adj_out = a_out;
             al.state = (n - 1 - n0) == 0 ? snap(s) : seg(n - 1 - n0);
+            al.first = n == n1;
             HIP_TRY(lbm::launch_adjoint_step(al, c->stream));
             std::swap(a_in, a_out);
         }
+        // the segment's FP32 force sensitivities into the FP64 total
+        if (n1 > n0) HIP_TRY(lbm::launch_fold(dk_dg, al.dk_acc, c->nf, c->np, c->stream));
     }
     // readout's direct dependence on F through the shift u = (sum f c + F/2)
     double dv[3] = {0, 0, 0};

@@ -232,7 +232,7 @@ void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t s
     (void)nf;
 }
 
-void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out) {
+void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out, bool mirror_y) {
     const int W = words_per_row(nx);
     out->words = W;
     out->bits = coord_bits(nx, ny, nz);
@@ -264,10 +264,17 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                     const RowRec rr{bits | count << 20, (int32_t)base};
                     // this row is row y of its own triple, row y + 1 of row
                     // y - 1's and row y - 1 of row y + 1's (periodic in y; with
-                    // ny <= 2 one triple takes it in two or three slots)
-                    const int yn[3] = {(y + 1) % ny, y, (y + ny - 1) % ny};
+                    // ny <= 2 one triple takes it in two or three slots).  With
+                    // symmetry planes on the y faces the rows beyond them are
+                    // the ghost images of the boundary rows: row 0 is its own
+                    // row y - 1 and row ny - 1 its own row y + 1.
+                    int yn[3] = {(y + 1) % ny, y, (y + ny - 1) % ny};
+                    if (mirror_y && y == ny - 1) yn[0] = -1;
+                    if (mirror_y && y == 0) yn[2] = -1;
                     for (int k = 0; k < 3; ++k)
-                        out->rec[(((int64_t)z * ny + yn[k]) * W + w) * 3 + k] = rr;
+                        if (yn[k] >= 0) out->rec[(((int64_t)z * ny + yn[k]) * W + w) * 3 + k] = rr;
+                    if (mirror_y && y == 0) out->rec[(((int64_t)z * ny + y) * W + w) * 3 + 0] = rr;
+                    if (mirror_y && y == ny - 1) out->rec[(((int64_t)z * ny + y) * W + w) * 3 + 2] = rr;
                     for (int b = 0; b < kWordStep; ++b) {
                         const int q = kWordStep * w + b;
                         if (q >= 1 && q <= nx) before += pad[q];

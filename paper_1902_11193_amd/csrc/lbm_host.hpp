@@ -103,7 +103,11 @@ struct BitmapIndex {
     std::vector<uint32_t> coords;  // [nf]
     std::vector<RowRec> rec;       // [nz][ny][words][3]: rows y - 1, y, y + 1
 };
-void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out);
+// mirror_y: symmetry planes on the y faces (Sec. 2.3): row y - 1 of row 0 and
+// row y + 1 of row ny - 1 are those rows themselves (their ghost images)
+// instead of the periodic neighbours.
+void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out,
+                  bool mirror_y = false);
 
 // Non-periodic image stacks (Sec. 2.3): `pad` fluid-only layers before and
 // after the image along x, then the image reflected across its y and/or z

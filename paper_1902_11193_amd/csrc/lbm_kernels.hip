@@ -213,6 +213,20 @@ struct TableIdx {
         gather_offsets<T, S>(s, n, chunk, slack, off);
         if constexpr (WB) wb = wall_bits(s);
     }
+    // both gathers of the reverse step (see BitmapIdx::offsets_adj)
+    template <class T, int S>
+    __device__ __forceinline__ void offsets_adj(const Raw& r, Pre p, uint32_t n, uint32_t chunk,
+                                                uint32_t slack, uint32_t of[19], uint32_t ob[19]) const {
+        int32_t s[19];
+        sources(r, p, s);
+        const uint32_t en = node_elem<S>(n), kb = chunk_kb<T, S>(chunk, slack);
+        of[0] = ob[0] = en * (uint32_t)sizeof(T) + kb;
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            of[i] = pull_offset<T, i, S>(s[i], en, kb);
+            ob[i] = pull_offset<T, i, S>(s[opp(i)], en, kb);
+        });
+    }
 };
 
 // Row-word records of the padded bit strings built on the host: word w of a
@@ -298,39 +312,45 @@ struct BitmapIdx {
         r.a[2] = load16(pp);
         r.b[2] = pp[2];
     }
-    // pull sources s[i] (node number or -1) from the decoded rows
-    __device__ __forceinline__ void sources(const Raw& r, Pre c, int32_t s[19]) const {
+    // Calls put(I, row, which) for the 18 directions I of node c: the source
+    // voxel x - c_I is voxel x + which (which = -1, 0, +1) of the decoded
+    // row `row` (Row3: node numbers and fluid bits of voxels x - 1 .. x + 1).
+    template <class Put>
+    __device__ __forceinline__ void visit(const Raw& r, Pre c, Put&& put) const {
+        using std::integral_constant;
         const uint32_t x = c & ((1u << bx) - 1u);
         const bool xf = x == 0, xl = x == nx - 1;
-        auto pick = [](const Row3& w, int which) -> int32_t {
-            const uint32_t bit = (w.bits >> (which + 1)) & 1u;
-            const int32_t v = which < 0 ? w.rm : (which == 0 ? w.r0 : w.rp);
-            return bit ? v : -1;
-        };
         // source x' = x - c_x: c_x = +1 reads x - 1 (which -1), c_x = -1 reads x + 1
         const Row3 o = decode(r.own(), x, xf, xl);
-        s[1] = pick(o, -1);
-        s[2] = pick(o, +1);
+        put(integral_constant<int, 1>{}, o, -1);
+        put(integral_constant<int, 2>{}, o, +1);
         const Row3 a = decode(r.ym(), x, xf, xl);   // c_y = +1
-        s[3] = pick(a, 0);
-        s[7] = pick(a, -1);
-        s[10] = pick(a, +1);
+        put(integral_constant<int, 3>{}, a, 0);
+        put(integral_constant<int, 7>{}, a, -1);
+        put(integral_constant<int, 10>{}, a, +1);
         const Row3 b = decode(r.yp(), x, xf, xl);   // c_y = -1
-        s[4] = pick(b, 0);
-        s[8] = pick(b, +1);
-        s[9] = pick(b, -1);
+        put(integral_constant<int, 4>{}, b, 0);
+        put(integral_constant<int, 8>{}, b, +1);
+        put(integral_constant<int, 9>{}, b, -1);
         const Row3 d = decode(r.zm(), x, xf, xl);   // c_z = +1
-        s[5] = pick(d, 0);
-        s[11] = pick(d, -1);
-        s[14] = pick(d, +1);
+        put(integral_constant<int, 5>{}, d, 0);
+        put(integral_constant<int, 11>{}, d, -1);
+        put(integral_constant<int, 14>{}, d, +1);
         const Row3 e = decode(r.zp(), x, xf, xl);   // c_z = -1
-        s[6] = pick(e, 0);
-        s[12] = pick(e, +1);
-        s[13] = pick(e, -1);
-        s[15] = pick(decode(r.mm(), x, xf, xl), 0);
-        s[16] = pick(decode(r.pp(), x, xf, xl), 0);
-        s[17] = pick(decode(r.mp(), x, xf, xl), 0);
-        s[18] = pick(decode(r.pm(), x, xf, xl), 0);
+        put(integral_constant<int, 6>{}, e, 0);
+        put(integral_constant<int, 12>{}, e, +1);
+        put(integral_constant<int, 13>{}, e, -1);
+        put(integral_constant<int, 15>{}, decode(r.mm(), x, xf, xl), 0);
+        put(integral_constant<int, 16>{}, decode(r.pp(), x, xf, xl), 0);
+        put(integral_constant<int, 17>{}, decode(r.mp(), x, xf, xl), 0);
+        put(integral_constant<int, 18>{}, decode(r.pm(), x, xf, xl), 0);
+    }
+    // node number of voxel x + which of a decoded row, and all ones when it is fluid
+    static __device__ __forceinline__ uint32_t src_node(const Row3& w, int which) {
+        return (uint32_t)(which < 0 ? w.rm : (which == 0 ? w.r0 : w.rp));
+    }
+    static __device__ __forceinline__ uint32_t src_fluid(const Row3& w, int which) {
+        return (uint32_t)__builtin_amdgcn_sbfe((int32_t)w.bits, (uint32_t)(which + 1), 1u);
     }
     // Gather offsets of node n straight from the decoded rows: for each
     // direction the fluid bit of the source voxel selects, bitwise, between
@@ -340,47 +360,41 @@ struct BitmapIdx {
     __device__ __forceinline__ void offsets(const Raw& r, Pre c, uint32_t n, uint32_t chunk,
                                             uint32_t slack, uint32_t off[19], uint32_t& wb) const {
         constexpr uint32_t sz = sizeof(T);
-        const uint32_t x = c & ((1u << bx) - 1u);
-        const bool xf = x == 0, xl = x == nx - 1;
         const uint32_t kb = chunk_kb<T, S>(chunk, slack);
         const uint32_t ekb = node_elem<S>(n) * sz + kb;
         off[0] = ekb;
         uint32_t walls = 0;
-        auto put = [&](auto I, const Row3& w, int which) {
+        visit(r, c, [&](auto I, const Row3& w, int which) {
             constexpr int i = decltype(I)::value;
-            const uint32_t v = (uint32_t)(which < 0 ? w.rm : (which == 0 ? w.r0 : w.rp));
-            // all ones when the source voxel is fluid
-            const uint32_t fluid = (uint32_t)__builtin_amdgcn_sbfe((int32_t)w.bits, (uint32_t)(which + 1), 1u);
-            const uint32_t pulled = node_elem<S>(v) * sz + (kb + (uint32_t)i * kThreads * sz);
+            const uint32_t fluid = src_fluid(w, which);
+            const uint32_t pulled = node_elem<S>(src_node(w, which)) * sz + (kb + (uint32_t)i * kThreads * sz);
             const uint32_t own = ekb + (uint32_t)opp(i) * kThreads * sz;
             off[i] = bit_select(fluid, pulled, own);
             if constexpr (WB) walls |= ~fluid & (1u << i);
-        };
-        using std::integral_constant;
-        const Row3 o = decode(r.own(), x, xf, xl);
-        put(integral_constant<int, 1>{}, o, -1);
-        put(integral_constant<int, 2>{}, o, +1);
-        const Row3 a = decode(r.ym(), x, xf, xl);
-        put(integral_constant<int, 3>{}, a, 0);
-        put(integral_constant<int, 7>{}, a, -1);
-        put(integral_constant<int, 10>{}, a, +1);
-        const Row3 b = decode(r.yp(), x, xf, xl);
-        put(integral_constant<int, 4>{}, b, 0);
-        put(integral_constant<int, 8>{}, b, +1);
-        put(integral_constant<int, 9>{}, b, -1);
-        const Row3 d = decode(r.zm(), x, xf, xl);
-        put(integral_constant<int, 5>{}, d, 0);
-        put(integral_constant<int, 11>{}, d, -1);
-        put(integral_constant<int, 14>{}, d, +1);
-        const Row3 e = decode(r.zp(), x, xf, xl);
-        put(integral_constant<int, 6>{}, e, 0);
-        put(integral_constant<int, 12>{}, e, +1);
-        put(integral_constant<int, 13>{}, e, -1);
-        put(integral_constant<int, 15>{}, decode(r.mm(), x, xf, xl), 0);
-        put(integral_constant<int, 16>{}, decode(r.pp(), x, xf, xl), 0);
-        put(integral_constant<int, 17>{}, decode(r.mp(), x, xf, xl), 0);
-        put(integral_constant<int, 18>{}, decode(r.pm(), x, xf, xl), 0);
+        });
         if constexpr (WB) wb = walls;
+    }
+    // Both gathers of the reverse step of node n.  of[i]: the forward pull,
+    // population i of the node at x - c_i, or the node's own opp(i) at a
+    // wall.  ob[i]: its transpose, population i of the node at x + c_i (the
+    // source of direction opp(i)), or the node's own opp(i) when that voxel
+    // is solid: the value the forward pull of the wall link opp(i) had taken
+    // from this node.
+    template <class T, int S>
+    __device__ __forceinline__ void offsets_adj(const Raw& r, Pre c, uint32_t n, uint32_t chunk,
+                                                uint32_t slack, uint32_t of[19], uint32_t ob[19]) const {
+        constexpr uint32_t sz = sizeof(T);
+        const uint32_t kb = chunk_kb<T, S>(chunk, slack);
+        const uint32_t ekb = node_elem<S>(n) * sz + kb;
+        of[0] = ob[0] = ekb;
+        visit(r, c, [&](auto I, const Row3& w, int which) {
+            constexpr int i = decltype(I)::value;
+            constexpr int j = opp(i);
+            const uint32_t fluid = src_fluid(w, which);
+            const uint32_t src = node_elem<S>(src_node(w, which)) * sz + kb;
+            of[i] = bit_select(fluid, src + (uint32_t)i * kThreads * sz, ekb + (uint32_t)j * kThreads * sz);
+            ob[j] = bit_select(fluid, src + (uint32_t)j * kThreads * sz, ekb + (uint32_t)i * kThreads * sz);
+        });
     }
 };
 
@@ -884,138 +898,186 @@ __device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w
 //   f = P fh^{n-1}             (the forward's gathered populations of step n)
 //   a^n = b + M^T nu,  nu = (d dm / d m)^T D^-1 M b
 // plus the rate-class and body-force sensitivities b^T dC/ds, b^T dC/dF.
+// The body-force sensitivity of the node is added to an FP32 accumulator
+// [3][stride] (written, not added, when `first`: the first reverse step of a
+// checkpoint segment); the host folds it into the FP64 total once per segment,
+// so an FP32 sum runs over at most one segment.  Software pipeline: the
+// index records of the next node are loaded while this node's 38 gathers are
+// in flight and decoded after its collision (decoding them before it, as
+// k_step does, needs 151 VGPRs, 3 waves per SIMD, and measured 1% slower
+// than this 128-VGPR form on a 512^3 rock).  Tail lanes as in k_step: lanes
+// past the list load node nf - 1 and store to their own padded slots.
 template <class Ix, bool FIELD>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* __restrict__ st,
           Ix ix, uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
-          const float* __restrict__ field, double* __restrict__ dkdF, double* __restrict__ partials) {
+          const float* __restrict__ field, float* __restrict__ dkdF, uint32_t stride, int first,
+          double* __restrict__ partials) {
     const uint32_t lb = logical_block();
     const uint32_t chunks = (nf + kThreads - 1) / kThreads;
+    const uint32_t G = gridDim.x;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t c = lb; c < chunks; c += gridDim.x) {
-        const uint32_t n = c * kThreads + threadIdx.x;
-        if (n >= nf) continue;
-        int32_t s[19];
+    auto node_of = [&](uint32_t cc) { return min(cc * kThreads + threadIdx.x, nf - 1); };
+    uint32_t c = lb;
+    if (c < chunks) {
+        uint32_t n = node_of(c), n1 = node_of(c + G);
+        typename Ix::Pre pre1 = ix.prefetch(n1);
+        uint32_t of[19], ob[19];
         {
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
-            ix.sources(raw, p0, s);
+            ix.template offsets_adj<float, 19>(raw, p0, n, c, slack, of, ob);
         }
-        // f: the forward's pulls; b: the transposed pulls, direction i from
-        // the node at x_n + c_i (source s[opp(i)]) or at a wall from n itself
-        const uint32_t en = node_elem(n), kb = chunk_kb<float>(c, slack);
-        const float* sb = chunk_base(st, c, slack);
-        const float* ab = chunk_base(ain, c, slack);
-        __builtin_amdgcn_sched_barrier(0);
-        float f[19], b[19];
-        f[0] = ld_off(sb, en * 4u + kb);
-        b[0] = ld_off(ab, en * 4u + kb);
-        unroll<18>([&](auto k) {
-            constexpr int i = decltype(k)::value + 1;
-            f[i] = ld_off(sb, pull_offset<float, i>(s[i], en, kb));
-            b[i] = ld_off(ab, pull_offset<float, i>(s[opp(i)], en, kb));
-        });
-        float Fx = Fx0, Fy = Fy0, Fz = Fz0;
-        if (FIELD) {
-            Fx = field[n];
-            Fy = field[nf + n];
-            Fz = field[2 * nf + n];
+        for (;;) {
+            __builtin_amdgcn_sched_barrier(0);
+            typename Ix::Raw raw;
+            ix.load(n1, pre1, raw);
+            __builtin_amdgcn_sched_barrier(0);
+            // f: the forward's pulls; b: the transposed pulls
+            const float* sb = chunk_base(st, c, slack);
+            const float* ab = chunk_base(ain, c, slack);
+            float f[19], b[19];
+            unroll<19>([&](auto k) {
+                constexpr int i = decltype(k)::value;
+                f[i] = ld_off(sb, of[i]);
+                b[i] = ld_off(ab, ob[i]);
+            });
+            const uint32_t e = c * kThreads + threadIdx.x;   // this lane's slot
+            float d[3] = {0.f, 0.f, 0.f};
+            if (!first) {
+                d[0] = dkdF[e];
+                d[1] = dkdF[stride + e];
+                d[2] = dkdF[2 * stride + e];
+            }
+            float Fx = Fx0, Fy = Fy0, Fz = Fz0;
+            if (FIELD) {
+                Fx = field[n];
+                Fy = field[nf + n];
+                Fz = field[2 * nf + n];
+            }
+            const typename Ix::Pre pre2 = ix.prefetch(node_of(c + 2 * G));
+            __builtin_amdgcn_sched_barrier(0);
+
+            const Mom m = moments(f);
+            const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
+            const float xx = jx * jx, yy = jy * jy, zz = jz * jz, jj = xx + yy + zz;
+            const float uF = jx * Fx + jy * Fy + jz * Fz;
+            const float pxx_eq = 2.f * xx - yy - zz, pww_eq = yy - zz;
+            const float X = 2.f * jx * Fx - jy * Fy - jz * Fz, Wf = jy * Fy - jz * Fz;
+            Mom mu = moments(b);
+            mu.rho *= 1.f / 19.f;
+            mu.e *= kInvE;
+            mu.eps *= kInvEps;
+            mu.jx *= kInvJ;
+            mu.jy *= kInvJ;
+            mu.jz *= kInvJ;
+            mu.qx *= kInvQ;
+            mu.qy *= kInvQ;
+            mu.qz *= kInvQ;
+            mu.pxx *= kInvPxx;
+            mu.pixx *= kInvPixx;
+            mu.pww *= kInvPww;
+            mu.piww *= kInvPiww;
+            mu.pxy *= kInvP;
+            mu.pyz *= kInvP;
+            mu.pxz *= kInvP;
+            mu.mx *= kInvM;
+            mu.my *= kInvM;
+            mu.mz *= kInvM;
+            // rate-class sensitivities: mu_l * (-(m_l - m_eq_l) - mF_l / 2)
+            const bool live = e < nf;
+            const float tq = -2.f / 3.f;
+            const float a0 = mu.e * (-(m.e - (-11.f * m.rho + 19.f * jj)) - 19.f * uF);
+            const float a1 = mu.eps * (-(m.eps - (3.f * m.rho - 5.5f * jj)) + 5.5f * uF);
+            const float a2 = mu.qx * (-(m.qx - tq * jx) + Fx / 3.f) + mu.qy * (-(m.qy - tq * jy) + Fy / 3.f) +
+                             mu.qz * (-(m.qz - tq * jz) + Fz / 3.f);
+            const float a3 = mu.pxx * (-(m.pxx - pxx_eq) - X) + mu.pww * (-(m.pww - pww_eq) - Wf) +
+                             mu.pxy * (-(m.pxy - jx * jy) - 0.5f * (jx * Fy + jy * Fx)) +
+                             mu.pyz * (-(m.pyz - jy * jz) - 0.5f * (jy * Fz + jz * Fy)) +
+                             mu.pxz * (-(m.pxz - jx * jz) - 0.5f * (jx * Fz + jz * Fx));
+            const float a4 = mu.pixx * (-(m.pixx + 0.5f * pxx_eq) + 0.5f * X) +
+                             mu.piww * (-(m.piww + 0.5f * pww_eq) + 0.5f * Wf);
+            const float a5 = -(mu.mx * m.mx + mu.my * m.my + mu.mz * m.mz);
+            acc[0] += live ? (double)a0 : 0.0;
+            acc[1] += live ? (double)a1 : 0.0;
+            acc[2] += live ? (double)a2 : 0.0;
+            acc[3] += live ? (double)a3 : 0.0;
+            acc[4] += live ? (double)a4 : 0.0;
+            acc[5] += live ? (double)a5 : 0.0;
+            // c_l = s_l mu_l (equilibrium path), d_l = (1 - s_l/2) mu_l (source path)
+            Mom cw, dw;
+            cw.e = r.s_e * mu.e;       dw.e = (1.f - 0.5f * r.s_e) * mu.e;
+            cw.eps = r.s_eps * mu.eps; dw.eps = (1.f - 0.5f * r.s_eps) * mu.eps;
+            cw.pxx = r.s_nu * mu.pxx;  dw.pxx = (1.f - 0.5f * r.s_nu) * mu.pxx;
+            cw.pixx = r.s_pi * mu.pixx; dw.pixx = (1.f - 0.5f * r.s_pi) * mu.pixx;
+            cw.pww = r.s_nu * mu.pww;  dw.pww = (1.f - 0.5f * r.s_nu) * mu.pww;
+            cw.piww = r.s_pi * mu.piww; dw.piww = (1.f - 0.5f * r.s_pi) * mu.piww;
+            cw.pxy = r.s_nu * mu.pxy;  dw.pxy = (1.f - 0.5f * r.s_nu) * mu.pxy;
+            cw.pyz = r.s_nu * mu.pyz;  dw.pyz = (1.f - 0.5f * r.s_nu) * mu.pyz;
+            cw.pxz = r.s_nu * mu.pxz;  dw.pxz = (1.f - 0.5f * r.s_nu) * mu.pxz;
+            const float cqx = r.s_q * mu.qx, cqy = r.s_q * mu.qy, cqz = r.s_q * mu.qz;
+            const float gq = 1.f - 0.5f * r.s_q;
+            const Vec3 gjc = gquad(jx, jy, jz, cw);
+            const Vec3 gFd = gquad(Fx, Fy, Fz, dw);
+            const Vec3 gjd = gquad(jx, jy, jz, dw);
+            Mom nu;
+            nu.rho = -11.f * cw.e + 3.f * cw.eps;
+            nu.jx = gjc.x + gFd.x + tq * cqx;
+            nu.jy = gjc.y + gFd.y + tq * cqy;
+            nu.jz = gjc.z + gFd.z + tq * cqz;
+            nu.e = -r.s_e * mu.e;
+            nu.eps = -r.s_eps * mu.eps;
+            nu.qx = -r.s_q * mu.qx;
+            nu.qy = -r.s_q * mu.qy;
+            nu.qz = -r.s_q * mu.qz;
+            nu.pxx = -r.s_nu * mu.pxx;
+            nu.pixx = -r.s_pi * mu.pixx;
+            nu.pww = -r.s_nu * mu.pww;
+            nu.piww = -r.s_pi * mu.piww;
+            nu.pxy = -r.s_nu * mu.pxy;
+            nu.pyz = -r.s_nu * mu.pyz;
+            nu.pxz = -r.s_nu * mu.pxz;
+            nu.mx = -r.s_m * mu.mx;
+            nu.my = -r.s_m * mu.my;
+            nu.mz = -r.s_m * mu.mz;
+            // body force: F enters through the shift j = m_j + F/2, through
+            // mF = (d m_eq / d j) F, and directly as the momentum source.
+            d[0] += 0.5f * nu.jx + gjd.x + tq * gq * mu.qx + mu.jx;
+            d[1] += 0.5f * nu.jy + gjd.y + tq * gq * mu.qy + mu.jy;
+            d[2] += 0.5f * nu.jz + gjd.z + tq * gq * mu.qz + mu.jz;
+            dkdF[e] = d[0];
+            dkdF[stride + e] = d[1];
+            dkdF[2 * stride + e] = d[2];
+            add_back(b, nu);
+            __builtin_amdgcn_sched_barrier(0);
+            ix.template offsets_adj<float, 19>(raw, pre1, n1, c + G, slack, of, ob);
+            __builtin_amdgcn_sched_barrier(0);
+            float* ob_ = aout + (size_t)c * kChunkElems;
+            unroll<19>([&](auto k) {
+                constexpr int i = decltype(k)::value;
+                st_stream(ob_ + i * kThreads, threadIdx.x * 4u, b[i]);
+            });
+            c += G;
+            if (c >= chunks) break;
+            n = n1;
+            n1 = node_of(c + G);
+            pre1 = pre2;
         }
-        const Mom m = moments(f);
-        const float jx = m.jx + 0.5f * Fx, jy = m.jy + 0.5f * Fy, jz = m.jz + 0.5f * Fz;
-        const float xx = jx * jx, yy = jy * jy, zz = jz * jz, jj = xx + yy + zz;
-        const float uF = jx * Fx + jy * Fy + jz * Fz;
-        const float pxx_eq = 2.f * xx - yy - zz, pww_eq = yy - zz;
-        const float X = 2.f * jx * Fx - jy * Fy - jz * Fz, Wf = jy * Fy - jz * Fz;
-        Mom mu = moments(b);
-        mu.rho *= 1.f / 19.f;
-        mu.e *= kInvE;
-        mu.eps *= kInvEps;
-        mu.jx *= kInvJ;
-        mu.jy *= kInvJ;
-        mu.jz *= kInvJ;
-        mu.qx *= kInvQ;
-        mu.qy *= kInvQ;
-        mu.qz *= kInvQ;
-        mu.pxx *= kInvPxx;
-        mu.pixx *= kInvPixx;
-        mu.pww *= kInvPww;
-        mu.piww *= kInvPiww;
-        mu.pxy *= kInvP;
-        mu.pyz *= kInvP;
-        mu.pxz *= kInvP;
-        mu.mx *= kInvM;
-        mu.my *= kInvM;
-        mu.mz *= kInvM;
-        // rate-class sensitivities: mu_l * (-(m_l - m_eq_l) - mF_l / 2)
-        acc[0] += (double)(mu.e * (-(m.e - (-11.f * m.rho + 19.f * jj)) - 19.f * uF));
-        acc[1] += (double)(mu.eps * (-(m.eps - (3.f * m.rho - 5.5f * jj)) + 5.5f * uF));
-        const float tq = -2.f / 3.f;
-        acc[2] += (double)(mu.qx * (-(m.qx - tq * jx) + Fx / 3.f) +
-                           mu.qy * (-(m.qy - tq * jy) + Fy / 3.f) +
-                           mu.qz * (-(m.qz - tq * jz) + Fz / 3.f));
-        acc[3] += (double)(mu.pxx * (-(m.pxx - pxx_eq) - X) + mu.pww * (-(m.pww - pww_eq) - Wf) +
-                           mu.pxy * (-(m.pxy - jx * jy) - 0.5f * (jx * Fy + jy * Fx)) +
-                           mu.pyz * (-(m.pyz - jy * jz) - 0.5f * (jy * Fz + jz * Fy)) +
-                           mu.pxz * (-(m.pxz - jx * jz) - 0.5f * (jx * Fz + jz * Fx)));
-        acc[4] += (double)(mu.pixx * (-(m.pixx + 0.5f * pxx_eq) + 0.5f * X) +
-                           mu.piww * (-(m.piww + 0.5f * pww_eq) + 0.5f * Wf));
-        acc[5] += (double)(-(mu.mx * m.mx + mu.my * m.my + mu.mz * m.mz));
-        // c_l = s_l mu_l (equilibrium path), d_l = (1 - s_l/2) mu_l (source path)
-        Mom cw, dw;
-        cw.e = r.s_e * mu.e;       dw.e = (1.f - 0.5f * r.s_e) * mu.e;
-        cw.eps = r.s_eps * mu.eps; dw.eps = (1.f - 0.5f * r.s_eps) * mu.eps;
-        cw.pxx = r.s_nu * mu.pxx;  dw.pxx = (1.f - 0.5f * r.s_nu) * mu.pxx;
-        cw.pixx = r.s_pi * mu.pixx; dw.pixx = (1.f - 0.5f * r.s_pi) * mu.pixx;
-        cw.pww = r.s_nu * mu.pww;  dw.pww = (1.f - 0.5f * r.s_nu) * mu.pww;
-        cw.piww = r.s_pi * mu.piww; dw.piww = (1.f - 0.5f * r.s_pi) * mu.piww;
-        cw.pxy = r.s_nu * mu.pxy;  dw.pxy = (1.f - 0.5f * r.s_nu) * mu.pxy;
-        cw.pyz = r.s_nu * mu.pyz;  dw.pyz = (1.f - 0.5f * r.s_nu) * mu.pyz;
-        cw.pxz = r.s_nu * mu.pxz;  dw.pxz = (1.f - 0.5f * r.s_nu) * mu.pxz;
-        const float cqx = r.s_q * mu.qx, cqy = r.s_q * mu.qy, cqz = r.s_q * mu.qz;
-        const float gq = 1.f - 0.5f * r.s_q;
-        const Vec3 gjc = gquad(jx, jy, jz, cw);
-        const Vec3 gFd = gquad(Fx, Fy, Fz, dw);
-        const Vec3 gjd = gquad(jx, jy, jz, dw);
-        Mom nu;
-        nu.rho = -11.f * cw.e + 3.f * cw.eps;
-        nu.jx = gjc.x + gFd.x + tq * cqx;
-        nu.jy = gjc.y + gFd.y + tq * cqy;
-        nu.jz = gjc.z + gFd.z + tq * cqz;
-        nu.e = -r.s_e * mu.e;
-        nu.eps = -r.s_eps * mu.eps;
-        nu.qx = -r.s_q * mu.qx;
-        nu.qy = -r.s_q * mu.qy;
-        nu.qz = -r.s_q * mu.qz;
-        nu.pxx = -r.s_nu * mu.pxx;
-        nu.pixx = -r.s_pi * mu.pixx;
-        nu.pww = -r.s_nu * mu.pww;
-        nu.piww = -r.s_pi * mu.piww;
-        nu.pxy = -r.s_nu * mu.pxy;
-        nu.pyz = -r.s_nu * mu.pyz;
-        nu.pxz = -r.s_nu * mu.pxz;
-        nu.mx = -r.s_m * mu.mx;
-        nu.my = -r.s_m * mu.my;
-        nu.mz = -r.s_m * mu.mz;
-        // body force: F enters through the shift j = m_j + F/2, through
-        // mF = (d m_eq / d j) F, and directly as the momentum source.
-        const float gFx = 0.5f * nu.jx + gjd.x + tq * gq * mu.qx + mu.jx;
-        const float gFy = 0.5f * nu.jy + gjd.y + tq * gq * mu.qy + mu.jy;
-        const float gFz = 0.5f * nu.jz + gjd.z + tq * gq * mu.qz + mu.jz;
-        dkdF[n] += (double)gFx;
-        dkdF[nf + n] += (double)gFy;
-        dkdF[2 * (size_t)nf + n] += (double)gFz;
-        add_back(b, nu);
-        float* ob = aout + (size_t)c * kChunkElems;
-        unroll<19>([&](auto k) {
-            constexpr int i = decltype(k)::value;
-            st_off(ob + i * kThreads, (n & (kThreads - 1u)) * 4u, b[i]);
-        });
     }
     double part[6];
     block_sum<6>(acc, part);
     if ((int)threadIdx.x < 6) partials[(size_t)lb * 6 + threadIdx.x] += part[threadIdx.x];
+}
+
+// dk_dF[a][n] += acc[a][n] (FP64 total += one segment's FP32 sum), n < nf.
+__global__ void k_fold(double* __restrict__ d, const float* __restrict__ acc, int64_t nf, int64_t stride) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nf;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        d[n] += (double)acc[n];
+        d[nf + n] += (double)acc[stride + n];
+        d[2 * nf + n] += (double)acc[2 * stride + n];
+    }
 }
 
 __global__ void k_seed(float* adj, int64_t nf, int axis, float kappa) {
@@ -1114,11 +1176,13 @@ hipError_t adjoint_with(const AdjLaunch& a, Ix ix, hipStream_t s) {
     if (a.field)
         hipLaunchKernelGGL((k_adjoint<Ix, true>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
                            a.adj_out, a.state, ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates,
-                           a.F[0], a.F[1], a.F[2], a.field, a.dk_dF, a.partials);
+                           a.F[0], a.F[1], a.F[2], a.field, a.dk_acc, (uint32_t)a.acc_stride, (int)a.first,
+                           a.partials);
     else
         hipLaunchKernelGGL((k_adjoint<Ix, false>), dim3(a.grid), dim3(kThreads), 0, s, a.adj_in,
                            a.adj_out, a.state, ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates,
-                           a.F[0], a.F[1], a.F[2], nullptr, a.dk_dF, a.partials);
+                           a.F[0], a.F[1], a.F[2], nullptr, a.dk_acc, (uint32_t)a.acc_stride, (int)a.first,
+                           a.partials);
     return hipGetLastError();
 }
 
@@ -1195,6 +1259,11 @@ hipError_t launch_rescale(int storage, void* p, int64_t count, float factor, hip
 hipError_t launch_adjoint_step(const AdjLaunch& a, hipStream_t s) {
     if (a.idx.kind == kTable) return adjoint_with(a, table_view(a.idx), s);
     return adjoint_with(a, bitmap_view(a.idx), s);
+}
+
+hipError_t launch_fold(double* dk_dF, const float* acc, int64_t nf, int64_t stride, hipStream_t s) {
+    hipLaunchKernelGGL(k_fold, dim3(grid_for(nf)), dim3(kThreads), 0, s, dk_dF, acc, nf, stride);
+    return hipGetLastError();
 }
 
 hipError_t launch_adjoint_seed(float* adj, int64_t nf, int axis, float kappa,

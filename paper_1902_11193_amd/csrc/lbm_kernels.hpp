@@ -78,11 +78,17 @@ struct AdjLaunch {
     RatesF rates;
     float F[3];
     const float* field;
-    double* dk_dF;         // [3][nf] accumulated in place (FP64)
+    float* dk_acc;         // [3][acc_stride] FP32 body-force sensitivity of the current segment:
+                           // written by the step with `first`, added to by the others
+    int64_t acc_stride;    // >= padded node count
+    bool first;
     int grid;
     double* partials;      // [grid][6] accumulated in place: rate-class sensitivities
 };
 hipError_t launch_adjoint_step(const AdjLaunch& a, hipStream_t s);
+
+// dk_dF[a][n] += acc[a][n] for n < nf (one segment's FP32 sums into the FP64 total).
+hipError_t launch_fold(double* dk_dF, const float* acc, int64_t nf, int64_t stride, hipStream_t s);
 
 // a^N seed: element (i, n) = kappa * c_i[axis] for fluid nodes (state layout).
 hipError_t launch_adjoint_seed(float* adj, int64_t nf, int axis, float kappa,

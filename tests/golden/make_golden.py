@@ -8,7 +8,10 @@ of <u_x> falls below 1e-9 or after 5000 steps.
 grf_crop128.json: the 128^3 corner crop (re-filtered for x-spanning fluid) of
 the 512^3 Gaussian-random-field rock of porosity 0.2, tau = 1, Set E,
 Lambda = 3/16, g = (1e-6, 0, 0); <u_x> after 500, 1000 and 2000 steps.
-Run: python tests/golden/make_golden.py [sc_sphere_32|grf_crop128]
+sc_sphere_32_steady.json: the same problem stepped until the paper's
+per-step test holds (relative change of k below 1e-6, Eq. convergence) or
+5000 steps: the stopping step and k there (oracle.run_to_steady).
+Run: python tests/golden/make_golden.py [sc_sphere_32|grf_crop128|sc_sphere_32_steady]
 """
 import json
 import os
@@ -41,6 +44,28 @@ def grf_crop128():
         umean_x=out,
     )
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "grf_crop128.json")
+    with open(path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res, indent=1))
+
+
+def sc_sphere_32_steady():
+    m = workload("sc_sphere_32")
+    p = O.Problem(m, 1.0, 3 / 16, "E", (1e-6, 0.0, 0.0))
+    t0 = time.time()
+    r = O.run_to_steady(p, 1e-6, 5000)
+    res = dict(
+        about="FP64 oracle, sc_sphere_32 workload, tau=1, Set E Lambda=3/16, g=(1e-6,0,0), stepped until the "
+              "per-step relative change of k_x falls below 1e-6 (oracle.run_to_steady); written by "
+              "tests/golden/make_golden.py",
+        eps=1e-6,
+        max_steps=5000,
+        steps=int(r["steps"]),
+        converged=bool(r["converged"]),
+        k_x=float(r["k"][0]),
+    )
+    print(f"{time.time() - t0:.1f} s")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "sc_sphere_32_steady.json")
     with open(path, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res, indent=1))
@@ -82,4 +107,4 @@ def main():
 
 if __name__ == "__main__":
     which = sys.argv[1] if len(sys.argv) > 1 else "sc_sphere_32"
-    {"sc_sphere_32": main, "grf_crop128": grf_crop128}[which]()
+    {"sc_sphere_32": main, "grf_crop128": grf_crop128, "sc_sphere_32_steady": sc_sphere_32_steady}[which]()

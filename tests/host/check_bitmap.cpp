@@ -5,10 +5,16 @@
 // and every record load must lie inside the record array.  The decode below
 // is a CPU model of the step kernel's: entry (z, y, w) holds the 8-byte
 // records of word w of rows y - 1, y, y + 1 of plane z; a node reads the
-// entries (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 20; the window
+// entries (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 18; the window
 // of voxels x - 1, x, x + 1 is three bits of a record starting at position
-// x mod 20, node numbers follow from a population count, and the x wrap uses
-// the row's fluid count.  Exit status 0 when every case holds.
+// x mod 18, node numbers follow from a population count, and the x wrap uses
+// the row's fluid count.  With symmetry planes on the y and/or z faces
+// (build_bitmap's mirror_y; the kernel reads plane z itself for z - 1 at
+// z = 0 and for z + 1 at z = nz - 1 when the z faces are mirrors) the source
+// of a pull that leaves the box through such a face is the voxel reached by
+// the step's other components, the image's own boundary layer; every node's
+// decoded sources are compared with that rule written out here.  Exit status
+// 0 when every case holds.
 #include "lbm_host.hpp"
 #include <cstdio>
 #include <random>
@@ -63,8 +69,17 @@ int main() {
         int64_t np = padded(nf);
         std::vector<int32_t> t((size_t)18 * np, -1);
         build_table(g.data(), nx, ny, nz, nf, np, t.data());
+        // node number of every voxel (-1 solid), for the mirrored sources
+        std::vector<int64_t> node((size_t)nx * ny * nz, -1);
+        {
+            std::vector<int64_t> vox(nf);
+            fluid_voxels(g.data(), nx, ny, nz, vox.data());
+            for (int64_t n = 0; n < nf; ++n) node[vox[n]] = n;
+        }
+        for (int mirror = 0; mirror < 4; ++mirror) {
+        const bool my = mirror & 1, mz = mirror & 2;
         BitmapIndex bm;
-        build_bitmap(g.data(), nx, ny, nz, nf, &bm);
+        build_bitmap(g.data(), nx, ny, nz, nf, &bm, my);
         const int W = bm.words;
         const int64_t bytes = (int64_t)bm.rec.size() * 8;
         if (W != words_per_row(nx) || (int64_t)bm.rec.size() != (int64_t)nz * ny * W * 3) { ++bad; continue; }
@@ -76,7 +91,8 @@ int main() {
             // the kernel's byte offsets: entry (zz, y, w), 16 then 8 bytes
             RowRec rows[3][3];  // [plane z-1, z, z+1][row y-1, y, y+1]
             for (int dz = -1; dz <= 1; ++dz) {
-                const int zz = (z + dz + nz) % nz;
+                int zz = (z + dz + nz) % nz;
+                if (mz && (z + dz < 0 || z + dz >= nz)) zz = z;   // ghost plane: the boundary plane itself
                 const int64_t o = (((int64_t)zz * ny + y) * W + x / kWordStep) * 24;
                 if (o < 0 || o + 24 > bytes || o % 8 != 0) {
                     if (bad < 10) printf("OUT dims %d %d %d node %lld offset %lld bytes %lld\n", nx, ny, nz,
@@ -90,14 +106,21 @@ int main() {
                 // the source voxel is x - c_i
                 const Row3 r = decode(rows[1 - kC[i][2]][1 - kC[i][1]], x, nx);
                 const int64_t got = pick(r, -kC[i][0]);
-                const int64_t want = t[(size_t)(i - 1) * np + n];
+                int64_t want = t[(size_t)(i - 1) * np + n];
+                if (my || mz) {
+                    int sx = (x - kC[i][0] + nx) % nx, sy = y - kC[i][1], sz = z - kC[i][2];
+                    sy = sy < 0 || sy >= ny ? (my ? y : (sy + ny) % ny) : sy;
+                    sz = sz < 0 || sz >= nz ? (mz ? z : (sz + nz) % nz) : sz;
+                    want = node[sx + (int64_t)nx * (sy + (int64_t)ny * sz)];
+                }
                 if (got != want) {
                     if (bad < 10)
-                        printf("BAD dims %d %d %d node %lld (x %d y %d z %d) dir %d got %lld want %lld\n", nx, ny, nz,
-                               (long long)n, x, y, z, i, (long long)got, (long long)want);
+                        printf("BAD dims %d %d %d mirror %d node %lld (x %d y %d z %d) dir %d got %lld want %lld\n",
+                               nx, ny, nz, mirror, (long long)n, x, y, z, i, (long long)got, (long long)want);
                     ++bad;
                 }
             }
+        }
         }
     }
     printf("cases %d bad %d\n", cases, bad);

@@ -52,7 +52,8 @@ def _run_pair(mask, rset, tau, Lam, index, nsteps_list, seed=0, g=G):
 @pytest.mark.parametrize("index", ["table", "bitmap"])
 def test_populations_match_oracle(name, make, index):
     mask = make()
-    for rset, tau, Lam in (("E", 0.8, 3 / 16), ("SRT", 1.1, None), ("C", 0.7, None), ("D", 1.3, None)):
+    for rset, tau, Lam in (("E", 0.8, 3 / 16), ("SRT", 1.1, None), ("A", 0.9, None), ("B", 0.65, None),
+                           ("C", 0.7, None), ("D", 1.3, None)):
         banner(f"populations {name} {index} {rset}")
         res = _run_pair(mask, rset, tau, Lam, index, [1, 2, 50])
         for n, (fg, fo, ug, uo) in res.items():
@@ -183,14 +184,24 @@ def test_run_to_steady_matches_oracle_step_count():
         assert abs(r["k"][0] / gold["k_final"] - 1) < 1e-6
 
 
-@pytest.mark.parametrize("storage,tol", [("f16", 1e-3), ("bf16", 1e-1), ("f16r", 2e-4)])
-def test_reduced_storage_permeability(storage, tol):
-    """k with FP16 / BF16 deviation storage against the FP64 oracle at equal N
-    on a 32^3 crop of the porosity-0.2 Gaussian-random-field rock.  This crop
-    is nearly blocked (k ~ 2e-3): density deviations exceed the velocity by
-    ~1e3, so the 8-bit BF16 mantissa resolves the flow only to ~1e-1.  FP16
-    with the per-node reference density rounds only the velocity-sized part
-    (measured 3.6e-5)."""
+def _record(name, **kw):
+    """Append a measurement to gpurun_out/storage_accuracy.jsonl (kept with the run's output)."""
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, "storage_accuracy.jsonl"), "a") as fh:
+        fh.write(json.dumps(dict(case=name, **kw)) + "\n")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16r", "f16", "bf16"])
+def test_reduced_storage_permeability(storage):
+    """k after 600 steps with each storage type against the FP64 oracle on a
+    32^3 crop of a porosity-0.2 Gaussian-random-field rock.  The crop is
+    nearly blocked (k ~ 2e-3): density deviations exceed the velocity by ~1e3.
+    FP32 storage is held to 1e-6 and FP16 relative to the per-node reference
+    density (which rounds only the velocity-sized part) to the 1e-3 FP16
+    target.  Plain FP16 and BF16 storage carry the density deviation in 11 and
+    8 mantissa bits; their errors are measured and printed, not held to a
+    bound."""
     rock = gaussian_random_field(64, 6.0, 0.2, seed=1904)
     m = crop(rock, 32)
     banner(f"reduced storage {storage} grf crop 32")
@@ -200,38 +211,48 @@ def test_reduced_storage_permeability(storage, tol):
     s = P.Solver(m, 1.0, 3 / 16, "E", (1e-6, 0, 0), storage=storage)
     s.step(N)
     k = s.permeability()[0]
-    print(f"[{storage}] crop32 k={k:.9g} oracle={ko:.9g} rel={k / ko - 1:.3e}")
-    assert abs(k / ko - 1) < tol
+    rel = k / ko - 1
+    print(f"[{storage}] crop32 k={k:.9g} oracle={ko:.9g} rel={rel:.3e}")
+    _record("grf64 crop32, 600 steps", storage=storage, k=k, k_oracle=ko, rel=rel)
+    assert np.isfinite(k)
+    if storage == "f32":
+        assert abs(rel) < 1e-6
+    elif storage == "f16r":
+        assert abs(rel) < 1e-3
 
 
-@pytest.mark.parametrize("storage,tol", [("f32", 1e-6), ("f16", 3e-2), ("bf16", 5e-1), ("f16r", 3e-5)])
-def test_grf_crop128_permeability_vs_oracle_golden(storage, tol):
-    """128^3 crop of the 512^3 rock: k after 500, 1000, 2000 steps with each
-    storage type against the FP64 oracle's values (tests/golden).  FP32 storage
-    meets 1e-6.  The crop is poorly connected (k ~ 2e-2) and pressure builds up
-    in its dead ends: density deviations grow to ~1e3 times the flow signal,
-    so FP16 storage (11-bit mantissa) drifts from ~1e-3 at 500-1000 steps to
-    ~1.5e-2 at 2000 steps; the bounds here are that measured envelope.  FP16
-    relative to the per-node reference density keeps the density part out of
-    the FP16 rounding and stays within 5e-6 (3e-5 allowed)."""
+@pytest.mark.parametrize("storage", ["f32", "f16r", "f16", "bf16"])
+def test_grf_crop128_permeability_vs_oracle_golden(storage):
+    """128^3 crop of the 512^3 rock: <u_x> after 500, 1000 and 2000 steps with
+    each storage type against the FP64 oracle's values (tests/golden).  FP32
+    storage is held to 1e-6; FP16 relative to the per-node reference density,
+    the FP16-storage path this library offers for rock, to 1e-5 (the 1e-3
+    target with margin; measured ~5e-6).  Plain FP16 and BF16 storage are
+    measured and printed: in this poorly connected crop (k ~ 2e-2) pressure
+    builds up in dead ends until the density deviation is ~1e3 times the flow
+    signal, which 11 or 8 mantissa bits cannot carry alongside it."""
     path = os.path.join(os.path.dirname(__file__), "golden", "grf_crop128.json")
-    if not os.path.exists(path):
-        pytest.skip("grf_crop128.json not generated")
     gold = json.load(open(path))
     m = crop(workload("grf_512"), 128)
     banner(f"grf crop128 {storage}")
     s = P.Solver(m, 1.0, 3 / 16, "E", (1e-6, 0, 0), storage=storage)
     assert s.n_fluid == gold["n_fluid"]
     done = 0
-    errs = []
+    errs = {}
     for n_str, ux in sorted(gold["umean_x"].items(), key=lambda kv: int(kv[0])):
         n = int(n_str)
         s.step(n - done)
         done = n
         rel = s.mean_velocity()[0] / ux - 1
         print(f"[{storage}] crop128 n={n} rel={rel:.3e}")
-        errs.append(abs(rel))
-    assert max(errs) < tol, (storage, errs)
+        errs[n] = float(rel)
+    _record("grf_512 crop128", storage=storage, rel_by_step=errs)
+    assert all(np.isfinite(list(errs.values())))
+    worst = max(abs(v) for v in errs.values())
+    if storage == "f32":
+        assert worst < 1e-6
+    elif storage == "f16r":
+        assert worst < 1e-5
 
 
 def test_force_field_uniform_equals_default():
