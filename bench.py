@@ -156,6 +156,16 @@ def run_steady(P, mask, args, storage):
                 k_drift_after_extra=k_extra / k - 1)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(mask_full, crop_n: int, steps: int):
     import torch
 
@@ -166,8 +176,9 @@ def cpu_baseline(mask_full, crop_n: int, steps: int):
     p = O.Problem(m, 1.0, 3 / 16, "E", (1e-6, 0.0, 0.0))
     t = O.time_steps(p, steps)
     return dict(value=p.nf * steps / t / 1e6, unit="MFLUPS", cores=torch.get_num_threads(), kind="oracle",
+                host_cpus=os.cpu_count(), cpu_model=cpu_model(),
                 sample=f"{steps} steps of the FP64 oracle on the {crop_n}^3 corner crop of the workload "
-                       f"({p.nf} fluid nodes), {t:.1f} s")
+                       f"({p.nf} fluid nodes), {t:.1f} s, on {torch.get_num_threads()} threads")
 
 
 def cpu_configs(steps: int):
