@@ -63,6 +63,12 @@ extern "C" {
 #define LBM_EHIP (-4)       /* a HIP runtime call failed; message has the HIP error string */
 #define LBM_ENAN (-5)       /* non-finite mean velocity or mass: the run diverged or overflowed */
 #define LBM_ERANGE (-6)     /* image too large for the index or gather layout */
+#define LBM_EBUSY (-7)      /* the GPU's static reduction scratch is held by another live context */
+
+/* Bytes of reduction scratch at the end of the workspace lbm_workspace_query
+ * sizes: per-block partial sums of the mean velocity and the ring of per-step
+ * sums.  lbm_setup_static keeps them in a static array instead. */
+#define LBM_REDUCTION_BYTES 557312
 
 /* Relaxation-rate sets of Table 2 (Sec. 2.2). */
 #define LBM_SRT 0
@@ -202,6 +208,24 @@ int lbm_neighbor_table(const uint8_t* geometry, int nx, int ny, int nz, int32_t*
 int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
               double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
               void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/* For callers that cannot allocate device memory at this point (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same as lbm_setup, except that the reduction scratch (LBM_REDUCTION_BYTES:
+ * two buffers of per-block partial sums and the ring of per-step sums) lives
+ * in a static device array of that size compiled into the library, one per
+ * GPU, held until the process ends, instead of at the end of `workspace`.
+ * `workspace` needs only lbm_workspace_query's bytes minus
+ * LBM_REDUCTION_BYTES; the library makes no device allocation.  One live
+ * context per GPU may hold the array: a second call on the same device
+ * returns LBM_EBUSY until the first context is destroyed.  The array keeps
+ * what the last context left in it; setup clears the ring and its step
+ * counter.  Launches that overlap on one GPU from outside the owning
+ * context's stream order would race on the array; the owning context's own
+ * calls are ordered on its stream.  Other errors as lbm_setup. */
+int lbm_setup_static(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
+                     double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
+                     void* workspace, size_t workspace_bytes, void* hip_stream);
 
 /* Advances n >= 0 time steps of Eq. LBE (Sec. 2): per step every fluid node
  * pulls f_i from x - c_i (halfway bounce-back where that voxel is solid),

@@ -20,6 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOFLUID, LBM_EWORKSPACE, LBM_EHIP, LBM_ENAN, LBM_ERANGE = 0, -1, -2, -3, -4, -5, -6
+LBM_EBUSY = -7
+LBM_REDUCTION_BYTES = 557312    # include/lbm.h
 SETS = {"SRT": 0, "A": 1, "B": 2, "C": 3, "D": 4, "E": 5}
 STORAGE = {"f32": 0, "f16": 1, "bf16": 2, "f16r": 3}
 INDEX = {"table": 0, "bitmap": 1}
@@ -36,6 +38,8 @@ SIGNATURES = {
     "lbm_node_order": (c_int, [POINTER(c_uint8), c_int, c_int, c_int, POINTER(c_int64), c_int64]),
     "lbm_setup": (c_int, [POINTER(c_void_p), POINTER(c_uint8), c_int, c_int, c_int, c_double, c_double, c_int,
                           POINTER(c_double), c_int, c_int, c_void_p, c_size_t, c_void_p]),
+    "lbm_setup_static": (c_int, [POINTER(c_void_p), POINTER(c_uint8), c_int, c_int, c_int, c_double, c_double,
+                                 c_int, POINTER(c_double), c_int, c_int, c_void_p, c_size_t, c_void_p]),
     "lbm_step": (c_int, [c_void_p, c_int]),
     "lbm_steps_done": (c_int64, [c_void_p]),
     "lbm_mean_velocity": (c_int, [c_void_p, POINTER(c_double)]),
@@ -184,7 +188,9 @@ class Solver:
     """One voxel image on one GPU: owns the library context and its workspace."""
 
     def __init__(self, geometry, tau: float, Lambda: float | None = None, relaxation_set="E",
-                 g=(1e-6, 0.0, 0.0), storage="f32", index="bitmap", device="cuda"):
+                 g=(1e-6, 0.0, 0.0), storage="f32", index="bitmap", device="cuda", static_scratch=False):
+        """static_scratch: set up with lbm_setup_static (the reduction scratch in
+        the library's static array; the workspace is LBM_REDUCTION_BYTES smaller)."""
         import torch
 
         self._torch = torch
@@ -194,16 +200,19 @@ class Solver:
         self.storage, self.index = storage, index
         self.relaxation_set = relaxation_set
         nbytes, self.n_fluid = lbm_workspace_query(gm, storage, index)
+        if static_scratch:
+            nbytes -= LBM_REDUCTION_BYTES
         self.device = torch.device(device)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.stream = torch.cuda.current_stream(self.device)
         ctx = c_void_p()
         gv = (c_double * 3)(*self.g)
         rs = SETS[relaxation_set] if isinstance(relaxation_set, str) else int(relaxation_set)
-        _check(lib().lbm_setup(byref(ctx), _dptr(gm, c_uint8), nx, ny, nz, self.tau,
-                               0.0 if Lambda is None else float(Lambda), rs, gv, STORAGE[storage],
-                               INDEX[index], c_void_p(self.workspace.data_ptr()), nbytes,
-                               c_void_p(self.stream.cuda_stream)))
+        setup = lib().lbm_setup_static if static_scratch else lib().lbm_setup
+        _check(setup(byref(ctx), _dptr(gm, c_uint8), nx, ny, nz, self.tau,
+                     0.0 if Lambda is None else float(Lambda), rs, gv, STORAGE[storage],
+                     INDEX[index], c_void_p(self.workspace.data_ptr()), nbytes,
+                     c_void_p(self.stream.cuda_stream)))
         self._ctx = ctx
         self._field = None
         self._wall_ws = None

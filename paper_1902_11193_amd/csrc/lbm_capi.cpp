@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -31,7 +32,8 @@ int fail(int code, const std::string& msg) {
 
 constexpr int kRing = (int)lbm::kRingSlots;
 constexpr int kGraphSteps = 32;  // steps per captured graph (even: the buffers return to place)
-constexpr int kMaxGrid = 8192;
+using lbm::kMaxGrid;
+using lbm::align256;
 constexpr double kW[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
 
 double weight(int i) {
@@ -43,8 +45,6 @@ double weight(int i) {
 size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
 // values kept per node: 19 populations, plus the reference density for LBM_F16R
 int slots(int storage) { return storage == LBM_F16R ? 20 : 19; }
-
-size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
@@ -69,13 +69,16 @@ Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int n
         L.rec = off;
         off += align256(recs * sizeof(lbm::RowRec));
     }
+    // the reduction scratch, kReductionBytes at the end (lbm_setup_static
+    // contexts keep it in the static array instead)
     L.partials = off;  // two buffers: steps alternate between them
-    off += 2 * align256((size_t)kMaxGrid * 4 * 8);
+    off += 2 * lbm::kPartialBytes;
     L.ring = off;  // ring of per-step sums, then the device counter of steps reduced
     off += align256((size_t)kRing * 4 * 8 + sizeof(uint32_t));
     L.total = off;
     return L;
 }
+static_assert(LBM_REDUCTION_BYTES == lbm::kReductionBytes, "header and layout disagree on the reduction scratch");
 
 std::string check_common(const uint8_t* geom, int nx, int ny, int nz, int storage,
                          int index_kind) {
@@ -150,11 +153,8 @@ struct lbm_ctx {
     bool graphs;
     hipStream_t cap_stream;
     hipGraphExec_t gexec[4];
-    ~lbm_ctx() {
-        for (auto& g : gexec)
-            if (g) hipGraphExecDestroy(g);
-        if (cap_stream) hipStreamDestroy(cap_stream);
-    }
+    int static_dev;  // device whose static reduction scratch this context holds, or -1
+    ~lbm_ctx();
 };
 
 namespace {
@@ -414,9 +414,35 @@ int lbm_boundary_image(const uint8_t* geometry, int nx, int ny, int nz, int pad,
     return LBM_OK;
 }
 
-int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
-              double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
-              void* workspace, size_t workspace_bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+// Contexts holding a GPU's static reduction scratch (lbm_setup_static), by device.
+constexpr int kStaticDevices = 64;
+std::mutex g_static_mu;
+const lbm_ctx* g_static_owner[kStaticDevices] = {};
+
+}  // namespace
+
+lbm_ctx::~lbm_ctx() {
+    for (auto& g : gexec)
+        if (g) hipGraphExecDestroy(g);
+    if (cap_stream) hipStreamDestroy(cap_stream);
+    if (static_dev >= 0) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[static_dev] == this) g_static_owner[static_dev] = nullptr;
+    }
+}
+
+namespace {
+
+// lbm_setup and lbm_setup_static: with use_static the reduction scratch is
+// the current GPU's static array instead of the workspace's last
+// LBM_REDUCTION_BYTES.
+int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau, double Lambda,
+               int relaxation_set, const double g[3], int storage, int index_kind, void* workspace,
+               size_t workspace_bytes, void* hip_stream, bool use_static) {
     if (!ctx) return fail(LBM_EINVAL, "ctx is NULL");
     *ctx = nullptr;
     std::string e = check_common(geometry, nx, ny, nz, storage, index_kind);
@@ -433,11 +459,23 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     if (rc != LBM_OK) return rc;
     if (!workspace) return fail(LBM_EWORKSPACE, "workspace is NULL");
     if (((uintptr_t)workspace & 255) != 0) return fail(LBM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (use_static) need -= LBM_REDUCTION_BYTES;  // the reduction scratch is the tail of the layout
     if (workspace_bytes < need)
         return fail(LBM_EWORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
 
     // ---- everything below may call HIP
+    void* red = nullptr;  // the static reduction scratch, when used
+    int dev = 0;
+    if (use_static) {
+        hipError_t he = hipGetDevice(&dev);
+        if (he != hipSuccess) return fail(LBM_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(he));
+        if (dev < 0 || dev >= kStaticDevices) return fail(LBM_ERANGE, "device ordinal beyond the static scratch table");
+        he = lbm::static_scratch(&red);
+        if (he != hipSuccess)
+            return fail(LBM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(he));
+    }
     auto* c = new lbm_ctx();
+    c->static_dev = -1;
     c->nx = nx;
     c->ny = ny;
     c->nz = nz;
@@ -461,10 +499,11 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     c->L = layout(c->np, nf, storage, index_kind, nx, ny, nz);
     c->cur = c->ws + c->L.A;
     c->nxt = c->ws + c->L.B;
-    c->partials[0] = reinterpret_cast<double*>(c->ws + c->L.partials);
-    c->partials[1] = c->partials[0] + align256((size_t)kMaxGrid * 4 * 8) / 8;
+    char* rbase = use_static ? static_cast<char*>(red) : c->ws + c->L.partials;  // partials, then the ring
+    c->partials[0] = reinterpret_cast<double*>(rbase);
+    c->partials[1] = c->partials[0] + lbm::kPartialBytes / 8;
     c->pending = false;
-    c->ring = reinterpret_cast<double*>(c->ws + c->L.ring);
+    c->ring = reinterpret_cast<double*>(rbase + (c->L.ring - c->L.partials));
     c->ctr = reinterpret_cast<uint32_t*>(c->ring + (size_t)kRing * 4);
     c->graphs = true;
     c->cap_stream = nullptr;
@@ -486,12 +525,19 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     c->wallbuf = nullptr;
     c->pressure = false;
     c->rho_in = c->rho_out = 1.0;
-    int dev = 0;
     c->cus = 0;
     auto cleanup = [&](int code) {
         delete c;
         return code;
     };
+    if (use_static) {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        if (g_static_owner[dev])
+            return cleanup(fail(LBM_EBUSY, "the static reduction scratch of device " + std::to_string(dev) +
+                                               " is held by another live context (lbm_destroy it first)"));
+        g_static_owner[dev] = c;
+        c->static_dev = dev;
+    }
     hipError_t he = hipGetDevice(&dev);
     if (he == hipSuccess) he = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("device query: ") + hipGetErrorString(he)));
@@ -532,6 +578,24 @@ int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, do
     if (he != hipSuccess) return cleanup(fail(LBM_EHIP, std::string("setup upload: ") + hipGetErrorString(he)));
     *ctx = c;
     return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_setup(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
+              double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
+              void* workspace, size_t workspace_bytes, void* hip_stream) {
+    return setup_impl(ctx, geometry, nx, ny, nz, tau, Lambda, relaxation_set, g, storage, index_kind, workspace,
+                      workspace_bytes, hip_stream, false);
+}
+
+int lbm_setup_static(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, double tau,
+                     double Lambda, int relaxation_set, const double g[3], int storage, int index_kind,
+                     void* workspace, size_t workspace_bytes, void* hip_stream) {
+    return setup_impl(ctx, geometry, nx, ny, nz, tau, Lambda, relaxation_set, g, storage, index_kind, workspace,
+                      workspace_bytes, hip_stream, true);
 }
 
 int lbm_step(lbm_ctx* c, int n) {

@@ -23,11 +23,17 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
 namespace lbm {
 namespace {
+
+// Reduction scratch of contexts set up with lbm_setup_static: every GPU holds
+// its own copy.  Host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[kReductionBytes];
 
 constexpr int kThreads = 256;
 
@@ -1187,6 +1193,25 @@ hipError_t adjoint_with(const AdjLaunch& a, Ix ix, hipStream_t s) {
 }
 
 }  // namespace
+
+hipError_t static_scratch(void** ptr) {
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static void* addr[kDevices] = {};
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he != hipSuccess) return he;
+    if (dev < 0 || dev >= kDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        he = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (he != hipSuccess) return he;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_step(const StepLaunch& a, hipStream_t s) {
     return a.collision == kTrt ? step_collision<true>(a, s) : step_collision<false>(a, s);

@@ -13,6 +13,19 @@ enum IndexKind : int { kTable = 0, kBitmap = 1 };
 enum Collision : int { kMrt = 0, kTrt = 1 };
 // Slots of the ring of per-step sums (ux, uy, uz, drho) kept on the device.
 constexpr uint32_t kRingSlots = 1024;
+// Most blocks a step launch uses (its per-block partial sums are sized for it).
+constexpr int kMaxGrid = 8192;
+// The reduction scratch of a context: two buffers of per-block partial sums
+// (double[kMaxGrid][4] each, 256-byte aligned) and the ring with its step
+// counter, in that order; the tail of a workspace, or the static array.
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+constexpr size_t kPartialBytes = align256((size_t)kMaxGrid * 4 * 8);
+constexpr size_t kReductionBytes = 2 * kPartialBytes + align256((size_t)kRingSlots * 4 * 8 + 4);
+
+// Device address of the current GPU's static reduction scratch (one array
+// of kReductionBytes per GPU, kept until the process ends), looked up once
+// per device.
+hipError_t static_scratch(void** ptr);
 
 struct RatesF {
     float s_e, s_eps, s_q, s_nu, s_pi, s_m;

@@ -174,15 +174,17 @@ def test_bitmap_row_length_limit():
         assert P.lbm_workspace_query(m, "f16", "table")[1] == nx
 
 
-def _setup_rc(mask, tau=1.0, Lam=0.1875, rset=5, g=(1e-6, 0, 0), storage=0, index=1, ws=None, nbytes=None):
-    """Call lbm_setup with a fake (never dereferenced) workspace; validation fails first."""
+def _setup_rc(mask, tau=1.0, Lam=0.1875, rset=5, g=(1e-6, 0, 0), storage=0, index=1, ws=None, nbytes=None,
+              fn="lbm_setup"):
+    """Call lbm_setup (or lbm_setup_static) with a fake (never dereferenced)
+    workspace; validation fails first."""
     L = P.lib()
     m = np.ascontiguousarray(mask, np.uint8)
     nz, ny, nx = m.shape
     ctx = ctypes.c_void_p()
     gv = (ctypes.c_double * 3)(*g)
-    rc = L.lbm_setup(ctypes.byref(ctx), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), nx, ny, nz, tau, Lam,
-                     rset, gv, storage, index, ws, nbytes if nbytes is not None else 0, None)
+    rc = getattr(L, fn)(ctypes.byref(ctx), m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), nx, ny, nz, tau, Lam,
+                        rset, gv, storage, index, ws, nbytes if nbytes is not None else 0, None)
     assert not ctx.value
     return rc
 
@@ -201,6 +203,24 @@ def test_setup_validates_before_any_device_call():
     assert _setup_rc(m, ws=fake, nbytes=16) == P.LBM_EWORKSPACE
     assert _setup_rc(m, ws=ctypes.c_void_p(4096 + 8), nbytes=1 << 40) == P.LBM_EWORKSPACE
     assert b"workspace" in P.lib().lbm_last_error()
+
+
+def test_setup_static_validates_and_needs_less_workspace():
+    """lbm_setup_static checks its arguments as lbm_setup does, before any
+    device call, and sizes the workspace without the reduction scratch."""
+    m = slit(4, 6, 4, 3)
+    fake = ctypes.c_void_p(4096)
+    hdr = open(HEADER).read()
+    assert f"#define LBM_REDUCTION_BYTES {P.LBM_REDUCTION_BYTES}" in hdr
+    assert f"#define LBM_EBUSY ({P.LBM_EBUSY})" in hdr
+    for bad in (dict(tau=0.5), dict(rset=6), dict(storage=5), dict(g=(float("nan"), 0, 0))):
+        assert _setup_rc(m, ws=fake, nbytes=1 << 40, fn="lbm_setup_static", **bad) == P.LBM_EINVAL
+    nbytes, _ = P.lbm_workspace_query(m, "f32", "bitmap")
+    need = nbytes - P.LBM_REDUCTION_BYTES
+    assert need > 0
+    assert _setup_rc(m, ws=fake, nbytes=need - 1, fn="lbm_setup_static") == P.LBM_EWORKSPACE
+    assert f"need {need} bytes".encode() in P.lib().lbm_last_error()
+    assert _setup_rc(m, ws=fake, nbytes=need, fn="lbm_setup") == P.LBM_EWORKSPACE
 
 
 def test_gather_span_bounds_brute_force(tmp_path):
