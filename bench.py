@@ -42,6 +42,9 @@ def index_bytes(index: str, shape, nf: int) -> float:
     return 4 + 24 * ny * nz * ((nx + 17) // 18) / nf
 # Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n.
 ADJ_ALG_BYTES = 3 * 19 * 4
+# ... and per node-step of the reverse sweep with its recompute: the recompute
+# step reads and writes a state (152 B) on top of the reverse step's 228 B.
+ADJ_RECOMPUTE_ALG_BYTES = ADJ_ALG_BYTES + 2 * 19 * 4
 
 
 def kernel_source_hash() -> str:
@@ -105,23 +108,44 @@ def run_forward(P, mask, args, storage, collision="mrt"):
                 steps_total=args.warmup + args.steps + args.steps % 2 + args.steps, wall_s=wall)
 
 
-def run_adjoint(P, mask, args):
+def run_adjoint(P, mask, args, N=None, K=None, g=None, label="grf_512"):
+    """The discrete adjoint: whole-job node-steps per second, and from the
+    library's event timing of its phases the reverse step's HBM roofline
+    (228 algorithmic bytes per node) and that of the reverse sweep with its
+    recompute (380 bytes per node-step)."""
     import torch
 
-    s = P.Solver(mask, args.tau, args.Lambda, "E", (args.g, 0.0, 0.0), "f32", args.index)
-    N, K = args.adj_steps, args.adj_checkpoint
+    N = N or args.adj_steps
+    K = K or args.adj_checkpoint
+    g = args.g if g is None else g
+    s = P.Solver(mask, args.tau, args.Lambda, "E", (g, 0.0, 0.0), "f32", args.index)
+    s.adjoint(min(N, 2 * K), K)        # untimed: first-launch costs
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     r = s.adjoint(N, K)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    ph = s.adjoint_timing()
     nf = s.n_fluid
+    out = dict(workload=label, n_fluid=nf, n_steps=N, checkpoint_every=K, seconds=t,
+               node_steps_per_s=nf * N / t, MFLUPS_equivalent=nf * N / t / 1e6,
+               k=r["k"], dk_dtau=r["dk_dtau"], dk_dLambda=r["dk_dLambda"], **ph)
     s.close()
     del s, r
     torch.cuda.empty_cache()
-    # node-steps of the whole adjoint: forward N, recompute ~N, reverse N-1
-    return dict(n_steps=N, checkpoint_every=K, seconds=t, node_steps_per_s=nf * N / t,
-                MFLUPS_equivalent=nf * N / t / 1e6)
+    nrev = N - 1
+    if nrev > 0 and ph["reverse_ms"] > 0:
+        rev_s = ph["reverse_ms"] * 1e-3 / nrev
+        ach = ADJ_ALG_BYTES * nf / rev_s / 1e9
+        out["reverse_step_us"] = rev_s * 1e6
+        out["roofline"] = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
+                               traffic=None, kernel="k_adjoint<BitmapIdx, false>",
+                               algorithmic_bytes_per_launch=ADJ_ALG_BYTES * nf)
+        both = (ph["reverse_ms"] + ph["recompute_ms"]) * 1e-3
+        ach2 = ADJ_RECOMPUTE_ALG_BYTES * nf * nrev / both / 1e9
+        out["roofline_with_recompute"] = dict(bound="hbm", achieved=ach2, peak=HBM_PEAK_GBS, unit="GB/s",
+                                              frac=ach2 / HBM_PEAK_GBS, bytes_per_node_step=ADJ_RECOMPUTE_ALG_BYTES)
+    return out
 
 
 def run_steady(P, mask, args, storage):
@@ -217,7 +241,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="grf_512")
     ap.add_argument("--index", default="bitmap", choices=["bitmap", "table"])
-    ap.add_argument("--variants", default="f16,bf16,f16r,trt,f16_trt,adjoint")
+    ap.add_argument("--variants", default="f16,bf16,f16r,trt,f16_trt,adjoint,adjoint_c4")
     ap.add_argument("--tau", type=float, default=1.0)
     ap.add_argument("--Lambda", type=float, default=3 / 16)
     ap.add_argument("--g", type=float, default=None)
@@ -280,6 +304,10 @@ def main():
                 variants[f"{v}_collision"]["k_rel_vs_mrt"] = variants[f"{v}_collision"]["k_after_timed"] / base["k_after_timed"] - 1
         elif v == "adjoint":
             variants["adjoint"] = run_adjoint(P, mask, args)
+        elif v == "adjoint_c4":
+            # the 128^3 sphere pack, 4000 steps, checkpoint every 200
+            variants["adjoint_c4"] = run_adjoint(P, workload("pack_128"), args, N=4000, K=200, g=1e-6,
+                                                 label="pack_128")
         print(f"[bench] {v} done", file=sys.stderr, flush=True)
 
     steady = None

@@ -329,6 +329,20 @@ int lbm_set_wall(lbm_ctx* ctx, int mode, void* workspace, size_t workspace_bytes
  * lbm_adjoint refuses a context with pressure faces. */
 int lbm_set_pressure(lbm_ctx* ctx, int enable, double rho_in, double rho_out);
 
+/* Host + device upload.  Symmetry (mirror) planes on the faces normal to y
+ * and/or z (Sec. 2.3, the lateral planes of the paper's sphere-pack setup):
+ * the box is no longer periodic across those faces; a population that a
+ * step would pull from beyond such a face comes from the boundary layer's own
+ * voxel reached by the other components of c_i, with its velocity mirrored in
+ * that axis (zero normal velocity and zero normal gradients at the plane,
+ * half a voxel outside the layer).  Halfway (or full-way) bounce-back applies
+ * where that voxel is solid.  The same problem as lbm_boundary_image's
+ * reflected image, without its 2x (4x) nodes.  Needs the bitmap index and
+ * FP32 storage, no pressure faces (else LBM_EINVAL); rebuilds the row
+ * records (synchronises the stream).  (0, 0) returns to the periodic box.
+ * lbm_adjoint refuses a context with symmetry planes. */
+int lbm_set_symmetry(lbm_ctx* ctx, int mirror_y, int mirror_z);
+
 /* Host only.  With enable != 0 (the default), lbm_step and
  * lbm_run_to_steady run stretches of 32 steps, once a step is pending, by
  * replaying a HIP graph captured from the same launches on first use (one
@@ -360,6 +374,12 @@ int lbm_adjoint_workspace_query(lbm_ctx* ctx, int n_steps, int checkpoint_every,
 int lbm_adjoint(lbm_ctx* ctx, int n_steps, int checkpoint_every, void* workspace,
                 size_t workspace_bytes, double* k, double* dk_dtau, double* dk_dLambda,
                 double* dk_dg);
+
+/* Host only.  Where the last completed lbm_adjoint on this context spent its
+ * GPU time, measured with HIP events on its stream: ms[0] the forward run
+ * from rest with its snapshots, ms[1] the recomputation of the checkpoint
+ * segments, ms[2] the reverse steps.  LBM_EINVAL before any. */
+int lbm_adjoint_timing(const lbm_ctx* ctx, double ms[3]);
 
 void lbm_destroy(lbm_ctx* ctx);
 

@@ -61,11 +61,13 @@ SIGNATURES = {
     "lbm_neighbor_nodes": (c_int, [c_void_p, c_int, c_int, c_int, c_void_p, c_int64, c_void_p]),
     "lbm_get_state_nodes": (c_int, [c_void_p, c_void_p, c_int64, c_void_p]),
     "lbm_set_graphs": (c_int, [c_void_p, c_int]),
+    "lbm_set_symmetry": (c_int, [c_void_p, c_int, c_int]),
     "lbm_boundary_dims": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_void_p, c_void_p, c_void_p]),
     "lbm_boundary_image": (c_int, [c_void_p, c_int, c_int, c_int, c_int, c_int, c_int, c_void_p]),
     "lbm_adjoint_workspace_query": (c_int, [c_void_p, c_int, c_int, POINTER(c_size_t)]),
     "lbm_adjoint": (c_int, [c_void_p, c_int, c_int, c_void_p, c_size_t, POINTER(c_double), POINTER(c_double),
                             POINTER(c_double), c_void_p]),
+    "lbm_adjoint_timing": (c_int, [c_void_p, POINTER(c_double)]),
     "lbm_destroy": (None, [c_void_p]),
     "lbm_last_error": (ctypes.c_char_p, []),
 }
@@ -312,6 +314,10 @@ class Solver:
         else:
             _check(lib().lbm_set_pressure(self._ctx, 1, float(rho_in), float(rho_out)))
 
+    def set_symmetry(self, mirror_y: bool, mirror_z: bool):
+        """Symmetry (mirror) planes on the y and/or z faces (bitmap index, FP32)."""
+        _check(lib().lbm_set_symmetry(self._ctx, int(bool(mirror_y)), int(bool(mirror_z))))
+
     def set_wall(self, kind: str):
         """'halfway' (default) or 'fullway' bounce-back (FP32 storage)."""
         if kind == "halfway":
@@ -337,6 +343,12 @@ class Solver:
                                  nb.value, byref(k), byref(dt), byref(dl), c_void_p(dg.data_ptr())))
         del ws
         return dict(k=k.value, dk_dtau=dt.value, dk_dLambda=dl.value, dk_dg=dg)
+
+    def adjoint_timing(self) -> dict:
+        """GPU milliseconds of the last adjoint: forward, recompute, reverse."""
+        ms = np.zeros(3)
+        _check(lib().lbm_adjoint_timing(self._ctx, _dptr(ms, c_double)))
+        return dict(forward_ms=ms[0], recompute_ms=ms[1], reverse_ms=ms[2])
 
     def close(self):
         if getattr(self, "_ctx", None) is not None and self._ctx.value:

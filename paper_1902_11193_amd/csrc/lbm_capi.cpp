@@ -154,6 +154,8 @@ struct lbm_ctx {
     hipStream_t cap_stream;
     hipGraphExec_t gexec[4];
     int static_dev;  // device whose static reduction scratch this context holds, or -1
+    double adj_ms[3];  // last lbm_adjoint: forward, recompute and reverse milliseconds
+    bool adj_timed;
     ~lbm_ctx();
 };
 
@@ -896,12 +898,32 @@ int lbm_set_pressure(lbm_ctx* c, int enable, double rho_in, double rho_out) {
     if (c->g[0] != 0 || c->g[1] != 0 || c->g[2] != 0 || c->field)
         return fail(LBM_EINVAL, "pressure faces need a context without body force");
     if (c->wall_mode != LBM_WALL_HALFWAY) return fail(LBM_EINVAL, "pressure faces need halfway bounce-back");
+    if (c->idx.sym) return fail(LBM_EINVAL, "pressure faces cannot be combined with symmetry planes");
     if (c->nx < 3) return fail(LBM_EINVAL, "pressure faces need nx >= 3");
     c->pressure = true;
     drop_graphs(c);
     c->rho_in = rho_in;
     c->rho_out = rho_out;
     c->axis = 0;
+    return LBM_OK;
+}
+
+int lbm_set_symmetry(lbm_ctx* c, int mirror_y, int mirror_z) {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    const int sym = (mirror_y ? 1 : 0) | (mirror_z ? 2 : 0);
+    if (sym && c->index_kind != LBM_INDEX_BITMAP) return fail(LBM_EINVAL, "symmetry planes need the bitmap index");
+    if (sym && c->storage != LBM_F32) return fail(LBM_EINVAL, "symmetry planes need FP32 storage");
+    if (sym && c->pressure) return fail(LBM_EINVAL, "symmetry planes cannot be combined with pressure faces");
+    if (sym == c->idx.sym) return LBM_OK;
+    // the records hold ghost rows beyond mirrored y faces (the z ghost planes
+    // are chosen in the kernel)
+    lbm::BitmapIndex bm;
+    lbm::build_bitmap(c->geom.data(), c->nx, c->ny, c->nz, c->nf, &bm, (sym & 1) != 0);
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.rec, bm.rec.data(), bm.rec.size() * sizeof(lbm::RowRec),
+                           hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->idx.sym = sym;
+    drop_graphs(c);
     return LBM_OK;
 }
 
@@ -925,6 +947,36 @@ int lbm_set_storage_exponent(lbm_ctx* c, int e) {
 
 // ---------------------------------------------------------------- adjoint
 namespace {
+// Events on the stream between the phases of a run; phase k of a mark lasts
+// until the next mark.  The events are destroyed with the timer.
+struct PhaseTimer {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    hipError_t mark(int k, hipStream_t s) {
+        hipEvent_t e = nullptr;
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) return he;
+        ev.push_back(e);
+        kind.push_back(k);
+        return hipEventRecord(e, s);
+    }
+    // after the stream has drained: milliseconds per phase kind (< n)
+    hipError_t totals(double* ms, int n) const {
+        for (int k = 0; k < n; ++k) ms[k] = 0.0;
+        for (size_t i = 0; i + 1 < ev.size(); ++i) {
+            float t = 0.f;
+            hipError_t he = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            if (he != hipSuccess) return he;
+            if (kind[i] >= 0 && kind[i] < n) ms[kind[i]] += t;
+        }
+        return hipSuccess;
+    }
+    ~PhaseTimer() {
+        for (auto e : ev) hipEventDestroy(e);
+    }
+};
+enum { kPhaseForward = 0, kPhaseRecompute = 1, kPhaseReverse = 2, kPhaseOther = 3 };
+
 struct AdjLayout {
     size_t snaps, seg, adjA, adjB, acc, part6, scratch4, out6, total;
     int nsnap;
@@ -967,7 +1019,8 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
     if (!c || !dk_dtau || !dk_dLambda || !dk_dg) return fail(LBM_EINVAL, "NULL argument");
     if (c->storage != LBM_F32) return fail(LBM_EINVAL, "the adjoint needs FP32 storage");
     if (c->wall_mode != LBM_WALL_HALFWAY) return fail(LBM_EINVAL, "the adjoint is built for halfway bounce-back");
-    if (c->pressure) return fail(LBM_EINVAL, "the adjoint is built for the body-force-driven periodic box");
+    if (c->pressure || c->idx.sym)
+        return fail(LBM_EINVAL, "the adjoint is built for the body-force-driven periodic box");
     if (N < 1 || K < 1) return fail(LBM_EINVAL, "need n_steps >= 1 and checkpoint_every >= 1");
     if (c->g[c->axis] == 0) return fail(LBM_EINVAL, "no body force");
     const AdjLayout A = adj_layout(c, N, K);
@@ -982,7 +1035,10 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
     double* scratch4 = (double*)(ws + A.scratch4);
     double* out6 = (double*)(ws + A.out6);
 
+    c->adj_timed = false;
+    PhaseTimer timer;
     // forward from rest to step N, keeping fh^{sK}
+    HIP_TRY(timer.mark(kPhaseForward, c->stream));
     HIP_TRY(lbm::launch_zero(c->cur, (int64_t)19 * c->np * 4, c->stream));
     HIP_TRY(zero_ring(c));
     c->steps = 0;
@@ -994,6 +1050,7 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
         int rc = do_steps(c, 1);
         if (rc) return rc;
     }
+    HIP_TRY(timer.mark(kPhaseOther, c->stream));
     double u[3];
     int rc = lbm_mean_velocity(c, u);
     if (rc) return rc;
@@ -1021,10 +1078,12 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
         const int n0 = s * K;                        // segment start: fh^{n0}
         const int n1 = std::min((s + 1) * K, nrev);  // last reverse step of the segment
         // recompute fh^{n0+1} .. fh^{n1-1}
+        HIP_TRY(timer.mark(kPhaseRecompute, c->stream));
         for (int t = 1; t < n1 - n0; ++t) {
             const void* src = t == 1 ? (const void*)snap(s) : (const void*)seg(t - 1);
             HIP_TRY(step_raw(c, src, seg(t), scratch4));
         }
+        HIP_TRY(timer.mark(kPhaseReverse, c->stream));
         for (int n = n1; n > n0; --n) {
             al.adj_in = a_in;
             al.adj_out = a_out;
@@ -1033,6 +1092,7 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
             HIP_TRY(lbm::launch_adjoint_step(al, c->stream));
             std::swap(a_in, a_out);
         }
+        HIP_TRY(timer.mark(kPhaseOther, c->stream));
         // the segment's FP32 force sensitivities into the FP64 total
         if (n1 > n0) HIP_TRY(lbm::launch_fold(dk_dg, al.dk_acc, c->nf, c->np, c->stream));
     }
@@ -1053,6 +1113,15 @@ int lbm_adjoint(lbm_ctx* c, int N, int K, void* workspace, size_t workspace_byte
     *dk_dtau = via_t + u[c->axis] / (3.0 * gref);  // nu = (tau - 1/2)/3 in k
     *dk_dLambda = c->set == LBM_SET_E ? via_l : 0.0;
     if (k_out) *k_out = k;
+    HIP_TRY(timer.totals(c->adj_ms, 3));
+    c->adj_timed = true;
+    return LBM_OK;
+}
+
+int lbm_adjoint_timing(const lbm_ctx* c, double ms[3]) {
+    if (!c || !ms) return fail(LBM_EINVAL, "NULL argument");
+    if (!c->adj_timed) return fail(LBM_EINVAL, "no lbm_adjoint has completed on this context");
+    for (int k = 0; k < 3; ++k) ms[k] = c->adj_ms[k];
     return LBM_OK;
 }
 

@@ -45,6 +45,15 @@ __host__ __device__ constexpr int cdir(int i, int a) {
     return t[i][a];
 }
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// index of c_i with its components along the axes in `mask` (bit a: axis a) negated
+__host__ __device__ constexpr int mirrored(int i, int mask) {
+    int want[3] = {cdir(i, 0), cdir(i, 1), cdir(i, 2)};
+    for (int a = 0; a < 3; ++a)
+        if (mask >> a & 1) want[a] = -want[a];
+    for (int j = 0; j < 19; ++j)
+        if (cdir(j, 0) == want[0] && cdir(j, 1) == want[1] && cdir(j, 2) == want[2]) return j;
+    return -1;
+}
 // lattice weights w_i: 1/3 rest, 1/18 axis (i = 1..6), 1/36 diagonal
 __host__ __device__ constexpr float wgt(int i) { return i == 0 ? 1.f / 3.f : (i <= 6 ? 1.f / 18.f : 1.f / 36.f); }
 
@@ -211,9 +220,11 @@ struct TableIdx {
         });
     }
     // gather offsets of node n (chunk `chunk`) and, if WB, its wall links
-    template <class T, int S, bool WB>
+    // (symmetry planes need the bitmap index)
+    template <class T, int S, bool WB, bool SYM = false>
     __device__ __forceinline__ void offsets(const Raw& r, Pre p, uint32_t n, uint32_t chunk,
                                             uint32_t slack, uint32_t off[19], uint32_t& wb) const {
+        static_assert(!SYM, "symmetry planes are built for the bitmap index");
         int32_t s[19];
         sources(r, p, s);
         gather_offsets<T, S>(s, n, chunk, slack, off);
@@ -252,6 +263,11 @@ struct BitmapIdx {
     const uint32_t* __restrict__ coords;
     const uint2* __restrict__ rec;
     uint32_t nx, ny, nz, R, bx, by;  // R: words per row
+    // entry offsets from plane z to the plane read as z - 1 at z = 0 and as
+    // z + 1 at z = nz - 1: the periodic wrap, or 0 (the plane itself, its
+    // ghost image) with symmetry planes on the z faces
+    uint32_t zlo, zhi;
+    uint32_t sym;  // symmetry planes: bit 0 on the y faces, bit 1 on the z faces
 
     // voxels x - 1, x, x + 1 of a row: fluid bits (bit 0..2) and node numbers
     struct Row3 {
@@ -305,8 +321,8 @@ struct BitmapIdx {
         const uint32_t z = (uint32_t)((uint64_t)c >> (bx + by));
         const uint32_t plane = ny * R;                          // entries per plane
         const uint32_t e = (z * ny + y) * R + x / kWordStep;    // entry (z, y, w)
-        const uint32_t em = e + (z == 0 ? (nz - 1) * plane : 0u - plane);
-        const uint32_t ep = e + (z == nz - 1 ? 0u - (nz - 1) * plane : plane);
+        const uint32_t em = e + (z == 0 ? zlo : 0u - plane);
+        const uint32_t ep = e + (z == nz - 1 ? zhi : plane);
         const uint2* pm = rec + (uint64_t)em * 3u;
         const uint2* p0 = rec + (uint64_t)e * 3u;
         const uint2* pp = rec + (uint64_t)ep * 3u;
@@ -362,7 +378,13 @@ struct BitmapIdx {
     // direction the fluid bit of the source voxel selects, bitwise, between
     // the pulled population and the node's own opposite one, so no node
     // number -1 is formed and tested.  WB: also the wall links as a mask.
-    template <class T, int S, bool WB>
+    //
+    // SYM: symmetry planes on the y and/or z faces (Sec. 2.3).  A pull that
+    // would leave the box through such a face reads the ghost row or plane,
+    // the boundary layer itself (the records and zlo / zhi), and takes the
+    // population whose velocity is mirrored in that axis: the mirror image
+    // of the flow on the other side of the plane sends it back.
+    template <class T, int S, bool WB, bool SYM = false>
     __device__ __forceinline__ void offsets(const Raw& r, Pre c, uint32_t n, uint32_t chunk,
                                             uint32_t slack, uint32_t off[19], uint32_t& wb) const {
         constexpr uint32_t sz = sizeof(T);
@@ -370,10 +392,30 @@ struct BitmapIdx {
         const uint32_t ekb = node_elem<S>(n) * sz + kb;
         off[0] = ekb;
         uint32_t walls = 0;
+        // nodes on a mirrored face: pulls with c_y = +1 leave through y = 0, ...
+        bool y0 = false, y1 = false, z0 = false, z1 = false;
+        if constexpr (SYM) {
+            const uint32_t y = (c >> bx) & ((1u << by) - 1u);
+            const uint32_t z = (uint32_t)((uint64_t)c >> (bx + by));
+            y0 = (sym & 1u) && y == 0;
+            y1 = (sym & 1u) && y == ny - 1;
+            z0 = (sym & 2u) && z == 0;
+            z1 = (sym & 2u) && z == nz - 1;
+        }
         visit(r, c, [&](auto I, const Row3& w, int which) {
             constexpr int i = decltype(I)::value;
             const uint32_t fluid = src_fluid(w, which);
-            const uint32_t pulled = node_elem<S>(src_node(w, which)) * sz + (kb + (uint32_t)i * kThreads * sz);
+            uint32_t pop = (uint32_t)i * kThreads * sz;
+            if constexpr (SYM) {
+                constexpr int cy = cdir(i, 1), cz = cdir(i, 2);
+                const bool my = cy > 0 ? y0 : (cy < 0 ? y1 : false);
+                const bool mz = cz > 0 ? z0 : (cz < 0 ? z1 : false);
+                constexpr uint32_t py = (uint32_t)mirrored(i, 2) * kThreads * sz;
+                constexpr uint32_t pz = (uint32_t)mirrored(i, 4) * kThreads * sz;
+                constexpr uint32_t pyz = (uint32_t)mirrored(i, 6) * kThreads * sz;
+                pop = my ? (mz ? pyz : py) : (mz ? pz : pop);
+            }
+            const uint32_t pulled = node_elem<S>(src_node(w, which)) * sz + (kb + pop);
             const uint32_t own = ekb + (uint32_t)opp(i) * kThreads * sz;
             off[i] = bit_select(fluid, pulled, own);
             if constexpr (WB) walls |= ~fluid & (1u << i);
@@ -691,12 +733,13 @@ k_finalize_ring(const double* __restrict__ partials, int grid, double* __restric
 // the halfway gather brought (the previous step's); only the node itself
 // touches its slots.
 // ZH: Zou-He pressure boundaries on the x faces (bitmap index only, which
-// knows each node's x).
+// knows each node's x).  SYM: symmetry planes on the y / z faces (bitmap
+// index, BitmapIdx::offsets).
 // The plain MRT step fits 96 VGPRs without spilling and then runs 5 waves per
 // SIMD (+0.8% FP32 on a 512^3 rock); the reference-density, link-wise TRT and
 // full-way variants would spill there and keep the compiler's choice.
-template <class C, class Ix, bool FIELD, bool TRT, bool FW, bool ZH = false>
-__global__ void __launch_bounds__(kThreads, (C::kRef || TRT || FW) ? 1 : 5)
+template <class C, class Ix, bool FIELD, bool TRT, bool FW, bool ZH = false, bool SYM = false>
+__global__ void __launch_bounds__(kThreads, (C::kRef || TRT || FW || SYM) ? 1 : 5)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
        uint32_t slack, uint32_t nf, RatesF r, float Fx0, float Fy0, float Fz0,
        const float* __restrict__ field, float scale, float inv, double* __restrict__ partials,
@@ -734,7 +777,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
-            ix.template offsets<T, S, FW || REF>(raw, p0, n, c, slack, off, wb);
+            ix.template offsets<T, S, FW || REF, SYM>(raw, p0, n, c, slack, off, wb);
             if constexpr (ZH) side = ix.x_face(p0);
         }
         for (;;) {
@@ -779,7 +822,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             __builtin_amdgcn_sched_barrier(0);
             const uint32_t wb_n = wb, side_n = side;
             {
-                ix.template offsets<T, S, FW || REF>(raw, pre1, n1, c + G, slack, off, wb);
+                ix.template offsets<T, S, FW || REF, SYM>(raw, pre1, n1, c + G, slack, off, wb);
                 if constexpr (ZH) side = ix.x_face(pre1);
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -1112,23 +1155,27 @@ int grid_for(int64_t n) {
 
 TableIdx table_view(const IndexView& v) { return TableIdx{v.table, (uint32_t)v.stride}; }
 BitmapIdx bitmap_view(const IndexView& v) {
+    const uint32_t plane = (uint32_t)v.ny * (uint32_t)v.R;         // entries per plane
+    const uint32_t wrap = (uint32_t)(v.nz - 1) * plane;
+    const bool mz = (v.sym & 2) != 0;
     return BitmapIdx{v.coords, static_cast<const uint2*>(v.rec), (uint32_t)v.nx, (uint32_t)v.ny,
-                     (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by};
+                     (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by,
+                     mz ? 0u : wrap, mz ? 0u : 0u - wrap, (uint32_t)v.sym};
 }
 
-template <class C, class Ix, bool TRT, bool FW>
+template <class C, class Ix, bool TRT, bool FW, bool SYM = false>
 hipError_t step_launch(const StepLaunch& a, Ix ix, hipStream_t s) {
     using T = typename C::T;
     const T* src = static_cast<const T*>(a.src);
     T* dst = static_cast<T*>(a.dst);
     if (a.field)
-        hipLaunchKernelGGL((k_step<C, Ix, true, TRT, FW>), dim3(a.grid), dim3(kThreads), 0, s, src, dst, ix,
-                           (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field, a.scale,
-                           a.inv_scale, a.partials, a.prev_partials, a.ring, a.ctr, a.wall);
+        hipLaunchKernelGGL((k_step<C, Ix, true, TRT, FW, false, SYM>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
+                           ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], a.field,
+                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.ring, a.ctr, a.wall, 0.f, 0.f);
     else
-        hipLaunchKernelGGL((k_step<C, Ix, false, TRT, FW>), dim3(a.grid), dim3(kThreads), 0, s, src, dst,
-                           ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
-                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.ring, a.ctr, a.wall);
+        hipLaunchKernelGGL((k_step<C, Ix, false, TRT, FW, false, SYM>), dim3(a.grid), dim3(kThreads), 0, s, src,
+                           dst, ix, (uint32_t)a.idx.slack, (uint32_t)a.nf, a.rates, a.F[0], a.F[1], a.F[2], nullptr,
+                           a.scale, a.inv_scale, a.partials, a.prev_partials, a.ring, a.ctr, a.wall, 0.f, 0.f);
     return hipGetLastError();
 }
 
@@ -1143,12 +1190,20 @@ hipError_t step_pressure(const StepLaunch& a, BitmapIdx ix, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Full-way bounce-back is built for FP32 storage only.
+// Full-way bounce-back is built for FP32 storage only; symmetry planes for
+// FP32 storage and the bitmap index, without pressure faces.
 template <class C, class Ix, bool TRT>
 hipError_t step_with(const StepLaunch& a, Ix ix, hipStream_t s) {
     if (a.pressure) {
         if constexpr (std::is_same<C, CodecF32>::value && std::is_same<Ix, BitmapIdx>::value) {
-            if (!a.wall && !a.field) return step_pressure<TRT>(a, ix, s);
+            if (!a.wall && !a.field && !a.idx.sym) return step_pressure<TRT>(a, ix, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (a.idx.sym) {
+        if constexpr (std::is_same<C, CodecF32>::value && std::is_same<Ix, BitmapIdx>::value) {
+            if (a.wall) return step_launch<C, Ix, TRT, true, true>(a, ix, s);
+            return step_launch<C, Ix, TRT, false, true>(a, ix, s);
         }
         return hipErrorInvalidValue;
     }

@@ -40,6 +40,8 @@ struct IndexView {
     const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
     const void* rec;            // kBitmap: [nz][ny][R][3] 8-byte records (rows y - 1, y, y + 1)
     int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = words per row
+    int sym;                    // kBitmap: symmetry planes, bit 0 on the y faces, bit 1 on the z faces
+                                // (the records then hold the y ghost rows)
 };
 
 struct StepLaunch {

@@ -120,3 +120,34 @@ def test_adjoint_full_size_pack_128_vs_finite_differences(rset, Lam):
         hl = 1e-3 * Lam
         fd_lam = (k_at(tau, Lam + hl) - k_at(tau, Lam - hl)) / (2 * hl)
         assert abs(r["dk_dLambda"] - fd_lam) < 1e-3 * max(abs(fd_lam), r["k"]), (r["dk_dLambda"], fd_lam)
+
+
+def test_adjoint_c4_settings_vs_oracle_golden():
+    """The adjoint's full-size settings (4000 steps, checkpoint every 200,
+    tau = 1, Set E, Lambda = 3/16) on the 32^3 crop of the 128^3 pack, against
+    the oracle's FP64 gradient stored by tests/golden/make_golden.py (itself
+    within ~1e-6 of FP64 central differences there): dk/dtau, dk/dLambda and
+    dk/dg_x at 512 seeded nodes to 1e-4."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pack_crop32_adjoint.json")))
+    m = crop(workload("pack_128"), 32)
+    banner("adjoint pack_128 crop32 N=4000 K=200 vs oracle golden")
+    s = P.Solver(m, 1.0, 3 / 16, "E", (1e-6, 0, 0), "f32", "bitmap")
+    assert s.n_fluid == gold["n_fluid"]
+    r = s.adjoint(gold["n_steps"], gold["segment"])
+    s.close()
+    k = gold["k"]
+    print(f"k {r['k']:.9g} vs {k:.9g}; dk/dtau {r['dk_dtau']:.6e} vs {gold['dk_dtau']:.6e}; "
+          f"dk/dLambda {r['dk_dLambda']:.9g} vs {gold['dk_dLambda']:.9g}")
+    assert abs(r["k"] / k - 1) < 1e-5
+    assert abs(r["dk_dtau"] - gold["dk_dtau"]) < 1e-4 * max(abs(gold["dk_dtau"]), k)
+    assert abs(r["dk_dLambda"] - gold["dk_dLambda"]) < 1e-4 * max(abs(gold["dk_dLambda"]), k)
+    perm = P.raster_permutation(m)            # raster position of every library node
+    where = np.empty_like(perm)
+    where[perm] = np.arange(len(perm))        # library node of every raster position
+    dg = r["dk_dg"][0].cpu().numpy()[where[np.array(gold["sample"])]]
+    err = np.abs(dg - np.array(gold["dk_dgx_sample"])).max() / gold["dk_dgx_max"]
+    print(f"dk/dg_x at {len(gold['sample'])} nodes: max error {err:.2e} of max |dk/dg_x|")
+    assert err < 1e-4
+    assert abs(float(r["dk_dg"][0].sum()) / gold["dk_dgx_sum"] - 1) < 1e-4

@@ -9,7 +9,7 @@ import torch
 
 import oracle as O
 import paper_1902_11193_amd as P
-from gpu_helpers import banner, dense_from_lib, lib_from_dense, random_state, deviation_error
+from gpu_helpers import banner, dense_from_lib, lib_from_dense, random_state, deviation_error, W_LIB
 from lbm_inputs import random_mask, sphere
 
 pytestmark = pytest.mark.gpu
@@ -208,4 +208,110 @@ def test_fullway_last_node_with_many_chunks_per_block():
         err = deviation_error(got, ref)
         print(f"step {n}: last node {err_last:.2e}, all nodes {err:.2e}", flush=True)
         assert err_last < 2e-6 and err < 2e-6, (n, err_last, err)
+    s.close()
+
+
+@pytest.mark.parametrize("shape,sym", [((6, 7, 13), "y"), ((6, 7, 13), "z"), ((6, 7, 13), "yz"),
+                                       ((2, 3, 11), "yz"), ((5, 1, 9), "y")])
+@pytest.mark.parametrize("wall", ["halfway", "fullway"])
+@pytest.mark.parametrize("collision", ["mrt", "trt"])
+def test_symmetry_planes_in_kernel_match_oracle(shape, sym, wall, collision):
+    """lbm_set_symmetry (mirror planes applied in the step kernel, Sec. 2.3)
+    against the oracle's symmetry planes on the same padded image, from a
+    random state, 1, 2 and 50 steps; thin boxes where one row or plane is both
+    faces included."""
+    mask = np.pad(random_mask(shape, 0.3, 21), ((0, 0), (0, 0), (2, 2)))
+    banner(f"symmetry planes in kernel {shape} {sym} {wall} {collision}")
+    s = P.Solver(mask, 0.9, 3 / 16, "E", G, "f32", "bitmap")
+    s.set_symmetry("y" in sym, "z" in sym)
+    s.set_collision(collision)
+    if wall == "fullway":
+        s.set_wall("fullway")
+    f0 = random_state(s.n_fluid, 6)
+    s.set_state(f0)
+    f0 = s.get_state()
+    p = O.Problem(mask, 0.9, 3 / 16, "E", G, symmetric=sym, fullway=wall == "fullway", collision=collision)
+    d0 = dense_from_lib(p, f0)
+    fh = torch.stack([d0, d0.clone()]) if wall == "fullway" else d0
+    done = 0
+    for n in (1, 2, 50):
+        s.step(n - done)
+        for _ in range(n - done):
+            fh, u = p.step(fh)
+        done = n
+        ref = lib_from_dense(p, fh[0] if wall == "fullway" else fh)
+        err = deviation_error(s.get_state(), ref)
+        assert err < 2e-6, (shape, sym, wall, collision, n, err)
+        # <u> sums momenta made of deviations of the random state's scale:
+        # its FP32 error is bounded on that scale, not on <u>'s own (~1e-2 of it)
+        uo = p.mean_velocity(u).numpy()
+        assert np.allclose(s.mean_velocity(), uo, rtol=0, atol=2e-6 * np.abs(ref - W_LIB[:, None]).max())
+    s.close()
+
+
+def test_symmetry_planes_with_force_field_match_oracle():
+    mask = np.pad(random_mask((7, 8, 10), 0.3, 22), ((0, 0), (0, 0), (3, 3)))
+    banner("symmetry planes with a force field")
+    rng = np.random.default_rng(5)
+    s = P.Solver(mask, 1.1, None, "B", (1e-4, 0, 0), "f32", "bitmap")
+    s.set_symmetry(True, True)
+    gf = (1e-4 * (1 + 0.5 * rng.standard_normal((3, s.n_fluid)))).astype(np.float32)
+    s.set_force_field(torch.from_numpy(gf).cuda())
+    s.step(40)
+    dense = np.zeros((3,) + mask.shape)
+    dense.reshape(3, -1)[:, P.lbm_node_order(mask)] = gf.astype(np.float64)
+    p = O.Problem(mask, 1.1, None, "B", (1e-4, 0, 0), g_field=dense, symmetric="yz")
+    r = O.run(p, 40)
+    assert deviation_error(s.get_state(), lib_from_dense(p, r["state"])) < 2e-6
+    s.close()
+
+
+def test_symmetry_planes_equal_the_reflected_image():
+    """The paper's sphere-pack setup (5 padding layers, mirror planes on the
+    lateral faces) on a 32^3 crop of the 128^3 pack: k from the in-kernel
+    symmetry planes equals k of the reflected periodic image (4x the nodes)
+    at equal step counts."""
+    from lbm_inputs import crop, workload
+    m = crop(workload("pack_128"), 32)
+    banner("symmetry planes vs reflected image, pack_128 crop 32")
+    padded = np.pad(m, ((0, 0), (0, 0), (5, 5)))
+    a = P.Solver(padded, 1.0, 3 / 16, "E", (1e-6, 0, 0), "f32", "bitmap")
+    a.set_symmetry(True, True)
+    big = P.lbm_boundary_image(m, 5, True, True)
+    b = P.Solver(big, 1.0, 3 / 16, "E", (1e-6, 0, 0), "f32", "bitmap")
+    assert b.n_fluid == 4 * a.n_fluid
+    for n in (100, 400):
+        a.step(n - a.steps_done)
+        b.step(n - b.steps_done)
+        ka, kb = a.permeability()[0], b.permeability()[0]
+        print(f"n={n}: k symmetry planes {ka:.9g}, reflected image {kb:.9g}")
+        assert abs(ka / kb - 1) < 1e-6
+    a.close()
+    b.close()
+
+
+def test_symmetry_plane_argument_errors():
+    mask = np.pad(random_mask((6, 7, 9), 0.3, 23), ((0, 0), (0, 0), (2, 2)))
+    banner("symmetry plane argument errors")
+    for storage, index in (("f32", "table"), ("f16", "bitmap"), ("f16r", "bitmap")):
+        s = P.Solver(mask, 0.9, 3 / 16, "E", (1e-4, 0, 0), storage, index)
+        with pytest.raises(P.LbmError) as e:
+            s.set_symmetry(True, False)
+        assert e.value.code == P.LBM_EINVAL
+        s.close()
+    s = P.Solver(mask, 0.9, 3 / 16, "E", (0, 0, 0), "f32", "bitmap")
+    s.set_pressure(1.001, 1.0)
+    with pytest.raises(P.LbmError):
+        s.set_symmetry(False, True)
+    s.set_pressure(None)
+    s.set_symmetry(False, True)
+    with pytest.raises(P.LbmError):
+        s.set_pressure(1.001, 1.0)
+    s.close()
+    s = P.Solver(mask, 0.9, 3 / 16, "E", (1e-4, 0, 0), "f32", "bitmap")
+    s.set_symmetry(True, True)
+    with pytest.raises(P.LbmError):
+        s.adjoint(10, 5)
+    s.set_symmetry(False, False)      # back to the periodic box: the adjoint runs
+    assert np.isfinite(s.adjoint(10, 5)["k"])
     s.close()

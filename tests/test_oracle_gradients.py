@@ -76,3 +76,22 @@ def test_slit_closed_form_gradients(rset, tau, Lam):
         assert abs(gr["dk_dtau"]) < 1e-6 * gr["k"]
     else:
         assert abs(gr["dk_dtau"] / (4 * H * (tau - 0.5) / (3 * Ly)) - 1) < 1e-6
+
+
+def test_stored_oracle_gradient_at_full_size_settings_agrees_with_finite_differences():
+    """tests/golden/pack_crop32_adjoint.json (written by make_golden.py from the
+    oracle alone): at the adjoint's full-size settings, 4000 steps with
+    segments of 200 on a 32^3 pack crop, the oracle's reverse-mode gradient
+    matches FP64 central differences of its own k -- h = 1e-4 in tau and
+    Lambda, a 1e-2 relative change of g_x at four single voxels -- to 1e-4."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "pack_crop32_adjoint.json")))
+    k = gold["k"]
+    assert abs(gold["dk_dtau"] - gold["fd_dk_dtau"]) < 1e-4 * max(abs(gold["fd_dk_dtau"]), k)
+    assert abs(gold["dk_dLambda"] / gold["fd_dk_dLambda"] - 1) < 1e-4
+    for node, fd in gold["fd_dk_dgx"].items():
+        adj = gold["dk_dgx_sample"][gold["sample"].index(int(node))]
+        assert abs(adj / fd - 1) < 1e-4, (node, adj, fd)
+    # Euler identity for the nearly linear scheme: sum g0 dk/dg = k
+    assert abs(gold["dk_dgx_sum"] * 1e-6 / k - 1) < 1e-4
