@@ -81,7 +81,8 @@ extern "C" {
 /* Storage type of the population deviations.
  * LBM_F32, LBM_F16, LBM_BF16: f_i - w_i rho0 (FP16 scaled by 2^e).
  * LBM_F16R: FP16 with a reference density per node.  A node also stores
- *   r = fp16(rho - rho0) of its own populations, and each population as
+ *   r = fp16(rho - rho0) of its own populations (in an array of one FP16 per
+ *   node after the populations of the state), and each population as
  *   2^e (f_i - w_i rho0 - w_i r); the node that pulls a value adds w_i r of
  *   the node it came from.  Both sides use the same stored r, so nothing is
  *   lost to the reference; FP16 rounds only the velocity and
@@ -148,7 +149,7 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
  * coordinates over 32 bits, nx above 4095 or 2^32 row words or more; or the
  * populations gathered around one 256-node chunk
  * spanning 4 GiB or more in the chosen storage (three 16-plane z-tiles of
- * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16, 40 for F16R). */
+ * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16/F16R). */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
 

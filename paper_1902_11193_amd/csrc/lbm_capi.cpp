@@ -43,8 +43,16 @@ double weight(int i) {
 }
 
 size_t elem_size(int storage) { return storage == LBM_F32 ? 4 : 2; }
-// values kept per node: 19 populations, plus the reference density for LBM_F16R
-int slots(int storage) { return storage == LBM_F16R ? 20 : 19; }
+// values per node in the chunks of a state: the 19 populations
+constexpr int kSlots = 19;
+// LBM_F16R: the state's reference array follows its chunks, one FP16 per
+// node in node order, np + 4 entries (a kernel reads 8-byte windows of it
+// that may start up to two entries before the last node)
+int64_t ref_elems(int storage, int64_t np) { return storage == LBM_F16R ? np + 4 : 0; }
+// bytes of one state, before alignment
+size_t state_bytes(int storage, int64_t np) {
+    return ((size_t)kSlots * np + (size_t)ref_elems(storage, np)) * elem_size(storage);
+}
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
@@ -54,7 +62,7 @@ struct Layout {
 Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int ny, int nz) {
     Layout L{};
     size_t off = 0;
-    const size_t state = align256((size_t)slots(storage) * np * elem_size(storage));
+    const size_t state = align256(state_bytes(storage, np));
     L.A = off;
     off += state;
     L.B = off;
@@ -348,7 +356,7 @@ int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int sto
         return fail(LBM_ERANGE, "the bitmap index holds rows of at most 4095 voxels");
     if (index_kind == LBM_INDEX_BITMAP && (int64_t)ny * nz * lbm::words_per_row(nx) >= ((int64_t)1 << 32))
         return fail(LBM_ERANGE, "the bitmap index holds fewer than 2^32 row words");
-    e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, slots(storage)), storage);
+    e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, kSlots), storage);
     if (!e.empty()) return fail(LBM_ERANGE, e);
     if (bytes) *bytes = layout(lbm::padded(nf), nf, storage, index_kind, nx, ny, nz).total;
     return LBM_OK;
@@ -513,7 +521,7 @@ int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, d
     c->steps = 0;
     c->field = nullptr;
     c->geom.assign(geometry, geometry + (size_t)nx * ny * nz);
-    c->span = lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, slots(storage));
+    c->span = lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, kSlots);
     double gmax = std::max({std::fabs(g[0]), std::fabs(g[1]), std::fabs(g[2])});
     // FP16 scale: plain deviations hold the density deviation, which grows to
     // ~1e2-1e3 g in rock; the referenced ones hold velocity-sized values only
@@ -713,13 +721,13 @@ int lbm_run_to_steady(lbm_ctx* c, double eps, int check_every, int max_steps, in
 
 int lbm_get_state(lbm_ctx* c, double* f) {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
-    const size_t es = elem_size(c->storage);
-    const int S = slots(c->storage);
-    std::vector<char> raw((size_t)S * c->np * es);
+    const int S = kSlots;
+    std::vector<char> raw(state_bytes(c->storage, c->np));
     HIP_TRY(hipMemcpyAsync(raw.data(), c->cur, raw.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     const double inv = 1.0 / std::ldexp(1.0, c->exponent);
     const _Float16* h16 = reinterpret_cast<const _Float16*>(raw.data());
+    const _Float16* ref = h16 + (size_t)S * c->np;  // LBM_F16R: the reference array
     for (int i = 0; i < 19; ++i) {
         const double w = weight(i);
         for (int64_t n = 0; n < c->nf; ++n) {
@@ -730,7 +738,7 @@ int lbm_get_state(lbm_ctx* c, double* f) {
             else if (c->storage == LBM_F16)
                 d = (double)(float)h16[at] * inv;
             else if (c->storage == LBM_F16R)
-                d = (double)((float)h16[at] * (float)inv + (float)w * (float)h16[lbm::state_elem(S - 1, n, S)]);
+                d = (double)((float)h16[at] * (float)inv + (float)w * (float)ref[n]);
             else
                 d = (double)from_bf16(reinterpret_cast<const uint16_t*>(raw.data())[at]);
             f[(size_t)i * c->nf + n] = w + d;
@@ -744,16 +752,21 @@ int lbm_get_state_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double*
     for (int64_t k = 0; k < count; ++k)
         if (nodes[k] < 0 || nodes[k] >= c->nf) return fail(LBM_EINVAL, "node number out of range");
     const size_t es = elem_size(c->storage);
-    const int S = slots(c->storage);
+    const int S = kSlots;
     const size_t chunk_bytes = (size_t)S * lbm::kChunk * es;
     std::vector<char> buf(chunk_bytes);
+    std::vector<_Float16> rbuf(lbm::kChunk);  // LBM_F16R: the chunk's references
     const double inv = 1.0 / std::ldexp(1.0, c->exponent);
     int64_t loaded = -1;
     for (int64_t k = 0; k < count; ++k) {
         const int64_t n = nodes[k], q = n / lbm::kChunk;
-        if (q != loaded) {  // the node's chunk holds all its values
+        if (q != loaded) {  // the node's chunk holds its populations
             HIP_TRY(hipMemcpyAsync(buf.data(), static_cast<char*>(c->cur) + (size_t)q * chunk_bytes, chunk_bytes,
                                    hipMemcpyDeviceToHost, c->stream));
+            if (c->storage == LBM_F16R)
+                HIP_TRY(hipMemcpyAsync(rbuf.data(),
+                                       static_cast<char*>(c->cur) + ((size_t)S * c->np + (size_t)q * lbm::kChunk) * es,
+                                       lbm::kChunk * es, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));
             loaded = q;
         }
@@ -767,8 +780,7 @@ int lbm_get_state_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double*
             else if (c->storage == LBM_F16)
                 d = (double)(float)h16[at] * inv;
             else if (c->storage == LBM_F16R)
-                d = (double)((float)h16[at] * (float)inv +
-                             (float)weight(i) * (float)h16[lbm::state_elem(S - 1, m, S)]);
+                d = (double)((float)h16[at] * (float)inv + (float)weight(i) * (float)rbuf[m]);
             else
                 d = (double)from_bf16(reinterpret_cast<const uint16_t*>(buf.data())[at]);
             f[(size_t)i * count + k] = weight(i) + d;
@@ -779,9 +791,8 @@ int lbm_get_state_nodes(lbm_ctx* c, const int64_t* nodes, int64_t count, double*
 
 int lbm_set_state(lbm_ctx* c, const double* f) {
     if (!c || !f) return fail(LBM_EINVAL, "NULL argument");
-    const size_t es = elem_size(c->storage);
-    const int S = slots(c->storage);
-    std::vector<char> raw((size_t)S * c->np * es, 0);
+    const int S = kSlots;
+    std::vector<char> raw(state_bytes(c->storage, c->np), 0);
     const double sc = std::ldexp(1.0, c->exponent);
     _Float16* h16 = reinterpret_cast<_Float16*>(raw.data());
     std::vector<float> ref;
@@ -791,7 +802,7 @@ int lbm_set_state(lbm_ctx* c, const double* f) {
             double d = -1.0;
             for (int i = 0; i < 19; ++i) d += f[(size_t)i * c->nf + n];
             const _Float16 r = (_Float16)(float)d;
-            h16[lbm::state_elem(S - 1, n, S)] = r;
+            h16[(size_t)S * c->np + n] = r;
             ref[n] = (float)r;
         }
     }
@@ -939,7 +950,8 @@ int lbm_set_storage_exponent(lbm_ctx* c, int e) {
     if (c->storage != LBM_F16 && c->storage != LBM_F16R) return LBM_OK;
     if (e < -60 || e > 60) return fail(LBM_EINVAL, "exponent out of range [-60, 60]");
     const float factor = std::ldexp(1.0f, e - c->exponent);
-    HIP_TRY(lbm::launch_rescale(c->storage, c->cur, (int64_t)slots(c->storage) * c->np, factor, c->stream));
+    // the populations only; LBM_F16R's references are not scaled
+    HIP_TRY(lbm::launch_rescale(c->storage, c->cur, (int64_t)kSlots * c->np, factor, c->stream));
     c->exponent = e;
     drop_graphs(c);
     return LBM_OK;

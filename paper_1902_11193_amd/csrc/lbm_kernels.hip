@@ -95,7 +95,8 @@ struct CodecBF16 {
 };
 
 // FP16 relative to a per-node reference density: a node stores, besides its
-// populations, r = fp16(drho) in a 20th slot, and each population as
+// populations, r = fp16(drho) in the state's reference array (one FP16 per
+// node in node order, after the chunks), and each population as
 // 2^e (f_i - w_i rho0 - w_i r).  A reader adds w_i r of the node the value
 // came from.  Writer and reader use the same stored r, so the reference is
 // exact; what FP16 rounds is only the velocity and non-equilibrium part,
@@ -103,7 +104,7 @@ struct CodecBF16 {
 // connected rock.
 struct CodecF16R {
     using T = _Float16;
-    static constexpr int kSlots = 20;
+    static constexpr int kSlots = 19;
     static constexpr bool kRef = true;
     static __device__ __forceinline__ float cvt(T v, float inv) { return (float)v * inv; }
     static __device__ __forceinline__ T enc(float v, float s) { return (_Float16)(v * s); }
@@ -230,6 +231,43 @@ struct TableIdx {
         gather_offsets<T, S>(s, n, chunk, slack, off);
         if constexpr (WB) wb = wall_bits(s);
     }
+    // F16R: byte offset in the reference array of the node each value comes
+    // from (the source, or the node itself at a wall), one load per direction
+    struct RefPlan {
+        uint32_t ro[19];
+    };
+    template <class T, int S>
+    __device__ __forceinline__ void offsets_ref(const Raw& r, Pre p, uint32_t n, uint32_t chunk, uint32_t slack,
+                                                uint32_t off[19], uint32_t& wb, RefPlan& plan) const {
+        int32_t s[19];
+        sources(r, p, s);
+        gather_offsets<T, S>(s, n, chunk, slack, off);
+        wb = wall_bits(s);
+        plan.ro[0] = n * (uint32_t)sizeof(T);
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            plan.ro[i] = (uint32_t)(s[i] < 0 ? (int32_t)n : s[i]) * (uint32_t)sizeof(T);
+        });
+    }
+    template <class T>
+    struct RefLoads {
+        T v[19];
+    };
+    template <class T, int S>
+    __device__ __forceinline__ void issue_refs(const RefPlan& plan, const T* rb, uint32_t, const uint32_t*,
+                                               uint32_t, uint32_t, RefLoads<T>& L) const {
+        unroll<19>([&](auto k) {
+            constexpr int i = decltype(k)::value;
+            L.v[i] = ld_off(rb, plan.ro[i]);
+        });
+    }
+    template <class T>
+    __device__ __forceinline__ void finish_refs(const RefPlan&, uint32_t, const RefLoads<T>& L, T rr[19]) const {
+        unroll<19>([&](auto k) {
+            constexpr int i = decltype(k)::value;
+            rr[i] = L.v[i];
+        });
+    }
     // both gathers of the reverse step (see BitmapIdx::offsets_adj)
     template <class T, int S>
     __device__ __forceinline__ void offsets_adj(const Raw& r, Pre p, uint32_t n, uint32_t chunk,
@@ -337,6 +375,17 @@ struct BitmapIdx {
     // Calls put(I, row, which) for the 18 directions I of node c: the source
     // voxel x - c_I is voxel x + which (which = -1, 0, +1) of the decoded
     // row `row` (Row3: node numbers and fluid bits of voxels x - 1 .. x + 1).
+    // The nine rows are numbered 0 own, 1 y - 1, 2 y + 1, 3 z - 1, 4 z + 1,
+    // 5 (y - 1, z - 1), 6 (y + 1, z + 1), 7 (y - 1, z + 1), 8 (y + 1, z - 1);
+    // direction i pulls from voxel x + which_of(i) of row row_of(i).
+    static __host__ __device__ constexpr int row_of(int i) {
+        constexpr int t[19] = {0, 0, 0, 1, 2, 3, 4, 1, 2, 2, 1, 3, 4, 4, 3, 5, 6, 7, 8};
+        return t[i];
+    }
+    static __host__ __device__ constexpr int which_of(int i) {
+        constexpr int t[19] = {0, -1, 1, 0, 0, 0, 0, -1, 1, -1, 1, -1, 1, -1, 1, 0, 0, 0, 0};
+        return t[i];
+    }
     template <class Put>
     __device__ __forceinline__ void visit(const Raw& r, Pre c, Put&& put) const {
         using std::integral_constant;
@@ -444,7 +493,113 @@ struct BitmapIdx {
             ob[j] = bit_select(fluid, src + (uint32_t)j * kThreads * sz, ekb + (uint32_t)i * kThreads * sz);
         });
     }
+
+    // F16R: the references of the nodes a step pulls from.  The sources in
+    // one row are voxels x - 1 .. x + 1, nodes r0 - 1 .. r0 + 1 (node numbers
+    // run along a row), so one 8-byte window of the reference array per row,
+    // starting at the even node (r0 - 1) & ~1 (4-byte aligned), holds them:
+    // nine loads instead of nineteen.  Across the periodic x wrap (x = 0 or
+    // nx - 1) the source at x -/+ 1 is the row's last / first node, outside the
+    // window; load_refs fetches those few separately.
+    struct RefPlan {
+        uint32_t ro[9];  // byte offset of each row's window in the reference array
+        uint64_t pos;    // bits 2i, 2i + 1: position of value i's source node in its row's window
+        uint32_t xw;     // bit 0: x == 0, bit 1: x == nx - 1, with nx >= 3 (sources across the wrap)
+    };
+    template <class T, int S>
+    __device__ __forceinline__ void offsets_ref(const Raw& r, Pre c, uint32_t n, uint32_t chunk, uint32_t slack,
+                                                uint32_t off[19], uint32_t& wb, RefPlan& plan) const {
+        constexpr uint32_t sz = sizeof(T);
+        const uint32_t kb = chunk_kb<T, S>(chunk, slack);
+        const uint32_t ekb = node_elem<S>(n) * sz + kb;
+        off[0] = ekb;
+        uint32_t walls = 0, e[9];
+        uint64_t pos = 0;
+        visit(r, c, [&](auto I, const Row3& w, int which) {
+            constexpr int i = decltype(I)::value;
+            constexpr int R = row_of(i);
+            const uint32_t fluid = src_fluid(w, which);
+            const uint32_t node = src_node(w, which);
+            const uint32_t pulled = node_elem<S>(node) * sz + (kb + (uint32_t)i * kThreads * sz);
+            off[i] = bit_select(fluid, pulled, ekb + (uint32_t)opp(i) * kThreads * sz);
+            walls |= ~fluid & (1u << i);
+            if constexpr (i == 1 || i == 3 || i == 4 || i == 5 || i == 6 || i >= 15) {  // first visit of row R
+                const uint32_t r0 = (uint32_t)w.r0;
+                e[R] = (r0 == 0u ? 0u : r0 - 1u) & ~1u;
+                plan.ro[R] = e[R] * sz;
+            }
+            pos |= (uint64_t)((node - e[R]) & 3u) << (2 * i);
+        });
+        pos |= (uint64_t)((n - e[0]) & 3u);   // the node itself, in its own row's window
+        wb = walls;
+        plan.pos = pos;
+        // one or two voxels per row: the wrapped sources are the node itself
+        // or its neighbour, inside the window
+        const uint32_t x = c & ((1u << bx) - 1u);
+        plan.xw = nx < 3 ? 0u : (x == 0 ? 1u : (x == nx - 1 ? 2u : 0u));
+    }
+    // Loads in flight for node n (issue_refs, before the next node's offsets
+    // overwrite the plan), then rr[i] = reference of the node value i came
+    // from, its own at a wall (finish_refs, with node n's plan and walls).
+    template <class T>
+    struct RefLoads {
+        uint64_t win[9];
+        T wrap[5];  // across the x wrap: sources of c_x = +1 (x = 0) or c_x = -1 (x = nx - 1)
+    };
+    template <class T, int S>
+    __device__ __forceinline__ void issue_refs(const RefPlan& plan, const T* rb, uint32_t wb, const uint32_t* off,
+                                               uint32_t chunk, uint32_t slack, RefLoads<T>& L) const {
+        typedef uint32_t U2 __attribute__((ext_vector_type(2), aligned(4)));
+        unroll<9>([&](auto k) {
+            constexpr int R = decltype(k)::value;
+            const U2 v = ld_off(reinterpret_cast<const U2*>(rb), plan.ro[R]);
+            L.win[R] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+        });
+        if (plan.xw) {
+            // Node m of a pulled value i from its offset: the load reads element
+            // chunk * S * 256 - slack + off / sizeof(T) of the state (64-bit:
+            // states pass 4 GiB), which is node_elem(m) + i * 256.
+            const bool left = plan.xw & 1u;  // x = 0: c_x = +1 pulls the row's last node
+            unroll<5>([&](auto k) {
+                constexpr int a = 2 * decltype(k)::value + 1;          // 1, 7, 9, 11, 13 ...
+                constexpr int il = a == 1 ? 1 : a + 4, ir = il + 1;    // ... and 2, 8, 10, 12, 14
+                const int i = left ? il : ir;
+                if (!((wb >> i) & 1u)) {
+                    const uint32_t o = left ? off[il] : off[ir];
+                    const uint64_t ne = (uint64_t)chunk * (S * kThreads) - slack + o / (uint32_t)sizeof(T) -
+                                        (uint64_t)i * kThreads;
+                    const uint32_t m = (uint32_t)(ne / (S * kThreads)) * kThreads + (uint32_t)(ne % (S * kThreads));
+                    L.wrap[decltype(k)::value] = ld_off(rb, m * (uint32_t)sizeof(T));
+                }
+            });
+        }
+    }
+    template <class T>
+    __device__ __forceinline__ void finish_refs(const RefPlan& plan, uint32_t wb, const RefLoads<T>& L,
+                                                T rr[19]) const {
+        auto pick = [&](int R, int i) -> T {
+            const uint32_t q = (uint32_t)(plan.pos >> (2 * i)) & 3u;
+            return __builtin_bit_cast(T, (uint16_t)(L.win[R] >> (16u * q)));
+        };
+        const T own = pick(0, 0);
+        rr[0] = own;
+        unroll<18>([&](auto k) {
+            constexpr int i = decltype(k)::value + 1;
+            T v = pick(row_of(i), i);
+            if constexpr (i <= 14 && i != 3 && i != 4 && i != 5 && i != 6) {
+                // the x-wrapped sources
+                constexpr int slot = i <= 2 ? 0 : (i - 5) / 2;
+                constexpr unsigned side = (i & 1) ? 1u : 2u;
+                if (plan.xw == side) v = L.wrap[slot];
+            }
+            rr[i] = ((wb >> i) & 1u) ? own : v;
+        });
+    }
 };
+static_assert(BitmapIdx::row_of(7) == 1 && BitmapIdx::which_of(7) == -1 && BitmapIdx::row_of(9) == 2 &&
+                  BitmapIdx::which_of(9) == -1 && BitmapIdx::row_of(13) == 4 && BitmapIdx::which_of(13) == -1 &&
+                  BitmapIdx::row_of(14) == 3 && BitmapIdx::which_of(14) == 1,
+              "row_of / which_of follow BitmapIdx::visit");
 
 // ------------------------------------------------------------------ moments
 // Moments of 19 values in the paper's order (rho, e, eps, jx, qx, jy, qy, jz,
@@ -771,13 +926,23 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
         uint32_t n = node_of(c), n1 = node_of(c + G);
         typename Ix::Pre pre1 = ix.prefetch(n1);
         uint32_t off[19];
-        uint32_t wb = 0;    // wall links of node n (FW only)
+        uint32_t wb = 0;    // wall links of node n (FW, REF)
         uint32_t side = 0;  // pressure face of node n (ZH only)
+        typename Ix::RefPlan plan;  // REF: where the references of node n's sources are
+        // REF: the reference arrays after the chunks of the two states
+        const T* rsrc = src + (size_t)chunks * (S * kThreads);
+        T* rdst = dst + (size_t)chunks * (S * kThreads);
+        auto resolve = [&](const typename Ix::Raw& raw, typename Ix::Pre p, uint32_t node, uint32_t chunk) {
+            if constexpr (REF)
+                ix.template offsets_ref<T, S>(raw, p, node, chunk, slack, off, wb, plan);
+            else
+                ix.template offsets<T, S, FW, SYM>(raw, p, node, chunk, slack, off, wb);
+        };
         {
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
             ix.load(n, p0, raw);
-            ix.template offsets<T, S, FW || REF, SYM>(raw, p0, n, c, slack, off, wb);
+            resolve(raw, p0, n, c);
             if constexpr (ZH) side = ix.x_face(p0);
         }
         for (;;) {
@@ -794,19 +959,11 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
                 constexpr int i = decltype(k)::value;
                 fr[i] = ld_off(gb, off[i]);
             });
-            // REF: the reference density of the node each value came from (its
-            // last slot): the source node, or the node itself at a wall
-            T rr[19];
-            if constexpr (REF) {
-                unroll<19>([&](auto k) {
-                    constexpr int i = decltype(k)::value;
-                    constexpr uint32_t sz = sizeof(T);
-                    constexpr uint32_t adj_pull = (uint32_t)(S - 1 - i) * kThreads * sz;
-                    constexpr uint32_t adj_wall = (uint32_t)(S - 1 - opp(i)) * kThreads * sz;
-                    const uint32_t adj = ((wb >> i) & 1u) ? adj_wall : adj_pull;
-                    rr[i] = ld_off(gb, off[i] + adj);
-                });
-            }
+            // REF: the reference density of the node each value came from: the
+            // source node, or the node itself at a wall
+            typename Ix::template RefLoads<T> refl;
+            if constexpr (REF) ix.template issue_refs<T, S>(plan, rsrc, wb, off, c, slack, refl);
+            const typename Ix::RefPlan plan_n = plan;
             float wv[19];
             float* wc = FW ? wall + (size_t)c * kChunkElems : nullptr;
             // a lane's own slot in chunk c: node c * 256 + lane, or for a lane
@@ -822,10 +979,12 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
             __builtin_amdgcn_sched_barrier(0);
             const uint32_t wb_n = wb, side_n = side;
             {
-                ix.template offsets<T, S, FW || REF, SYM>(raw, pre1, n1, c + G, slack, off, wb);
+                resolve(raw, pre1, n1, c + G);
                 if constexpr (ZH) side = ix.x_face(pre1);
             }
             __builtin_amdgcn_sched_barrier(0);
+            T rr[19];
+            if constexpr (REF) ix.finish_refs(plan_n, wb_n, refl, rr);
             float f[19];
             unroll<19>([&](auto k) {
                 constexpr int i = decltype(k)::value;
@@ -887,7 +1046,7 @@ k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, I
                 // collision conserves, rounded to the stored type
                 const T r_new = (T)drho;
                 const float rf = (float)r_new;
-                st_stream(db + (S - 1) * kThreads, so, r_new);
+                st_stream(rdst + (size_t)c * kThreads, so, r_new);
                 unroll<19>([&](auto k) {
                     constexpr int i = decltype(k)::value;
                     st_stream(db + i * kThreads, so, C::enc(f[i] - wgt(i) * rf, scale));
@@ -918,9 +1077,6 @@ template <class C>
 __global__ void k_rescale(typename C::T* p, int64_t count, float factor) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        if constexpr (C::kRef) {
-            if ((i / kThreads) % C::kSlots == C::kSlots - 1) continue;  // reference slot: unscaled
-        }
         p[i] = C::enc(C::cvt(p[i], 1.f), factor);
     }
 }
