@@ -252,11 +252,18 @@ hipGraphExec_t graph_for(lbm_ctx* c) {
 }
 
 // One resident wave of blocks: every block starts at once and walks the
-// chunk list with stride `grid` (a multiple of the XCD count when >= 64).
+// chunk list with stride `grid` (a multiple of the XCD count when >= 64),
+// so the chunks in flight form a window of `grid` consecutive chunks.  With
+// FP32 storage one block per compute unit: that step is bound by the L2
+// misses of its gathers, not by latency, and the narrowest window serves
+// them best (512^3 rock: 0.833 ms with 5 blocks per unit, 0.827 with 2,
+// 0.769 with 1).  The 16-bit storages, bound by the loads they can keep in
+// flight, take every block that fits (1 per unit: FP16 0.575 -> 0.670 ms).
 hipError_t choose_grid(lbm_ctx* c) {
     int per_cu = 0;
     hipError_t he = lbm::step_occupancy(c->storage, c->index_kind, c->collision, &per_cu);
     if (he != hipSuccess) return he;
+    if (c->storage == LBM_F32) per_cu = 1;
     const int64_t chunks = (c->nf + 255) / 256;
     int64_t G = std::min<int64_t>(chunks, (int64_t)std::max(c->cus, 1) * std::max(per_cu, 1));
     if (G >= 64) G -= G % 8;

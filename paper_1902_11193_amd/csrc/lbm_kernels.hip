@@ -1106,12 +1106,13 @@ __device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w
 // The body-force sensitivity of the node is added to an FP32 accumulator
 // [3][stride] (written, not added, when `first`: the first reverse step of a
 // checkpoint segment); the host folds it into the FP64 total once per segment,
-// so an FP32 sum runs over at most one segment.  Software pipeline: the
-// index records of the next node are loaded while this node's 38 gathers are
-// in flight and decoded after its collision (decoding them before it, as
-// k_step does, needs 151 VGPRs, 3 waves per SIMD, and measured 1% slower
-// than this 128-VGPR form on a 512^3 rock).  Tail lanes as in k_step: lanes
-// past the list load node nf - 1 and store to their own padded slots.
+// so an FP32 sum runs over at most one segment.  Software pipeline as in
+// k_step: the index records of the next node are loaded and decoded while
+// this node's 38 gathers are in flight.  It is launched with one block per
+// compute unit (its two gathered arrays make it bound by L2 misses, not by
+// latency), where the registers this pipeline needs (151) cost no occupancy.
+// Tail lanes as in k_step: lanes past the list load node nf - 1 and store to
+// their own padded slots.
 template <class Ix, bool FIELD>
 __global__ void __launch_bounds__(kThreads)
 k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* __restrict__ st,
@@ -1162,6 +1163,8 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
                 Fz = field[2 * nf + n];
             }
             const typename Ix::Pre pre2 = ix.prefetch(node_of(c + 2 * G));
+            __builtin_amdgcn_sched_barrier(0);
+            ix.template offsets_adj<float, 19>(raw, pre1, n1, c + G, slack, of, ob);
             __builtin_amdgcn_sched_barrier(0);
 
             const Mom m = moments(f);
@@ -1255,9 +1258,6 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
             dkdF[stride + e] = d[1];
             dkdF[2 * stride + e] = d[2];
             add_back(b, nu);
-            __builtin_amdgcn_sched_barrier(0);
-            ix.template offsets_adj<float, 19>(raw, pre1, n1, c + G, slack, of, ob);
-            __builtin_amdgcn_sched_barrier(0);
             float* ob_ = aout + (size_t)c * kChunkElems;
             unroll<19>([&](auto k) {
                 constexpr int i = decltype(k)::value;
