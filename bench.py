@@ -40,16 +40,23 @@ def index_bytes(index: str, shape, nf: int) -> float:
         return 18 * 4
     nz, ny, nx = shape
     return 4 + 24 * ny * nz * ((nx + 17) // 18) / nf
-# Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n.
-ADJ_ALG_BYTES = 3 * 19 * 4
-# ... and per node-step of the reverse sweep with its recompute: the recompute
-# step reads and writes a state (152 B) on top of the reverse step's 228 B.
-ADJ_RECOMPUTE_ALG_BYTES = ADJ_ALG_BYTES + 2 * 19 * 4
+# Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n
+# (228 B), and update the node's running FP32 sum of dk/dg(x) (read 12 B,
+# write 12 B; the first step of a checkpoint segment writes it only).
+ADJ_POP_BYTES = 3 * 19 * 4
+ADJ_ACC_BYTES = 2 * 3 * 4
+ADJ_ALG_BYTES = ADJ_POP_BYTES + ADJ_ACC_BYTES
+# The reverse sweep also recomputes the states inside each checkpoint segment:
+# K - 1 forward steps per segment of K reverse steps, 152 B per node each.
 
 
 def kernel_source_hash() -> str:
-    p = os.path.join(ROOT, "paper_1902_11193_amd", "csrc", "lbm_kernels.hip")
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+    """sha256[:16] of the sources that set a step's memory traffic: the
+    kernels and the host code that orders the nodes."""
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_host.cpp", "lbm_host.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1902_11193_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_for(workload: str, storage: str, index: str):
@@ -111,8 +118,10 @@ def run_forward(P, mask, args, storage, collision="mrt"):
 def run_adjoint(P, mask, args, N=None, K=None, g=None, label="grf_512"):
     """The discrete adjoint: whole-job node-steps per second, and from the
     library's event timing of its phases the reverse step's HBM roofline
-    (228 algorithmic bytes per node) and that of the reverse sweep with its
-    recompute (380 bytes per node-step)."""
+    (252 algorithmic bytes per node, 240 on the first step of a segment; the
+    fraction over the 228 population bytes alone beside it) and that of the
+    reverse sweep with its recompute (a 152-byte forward step per node for all
+    but one of a segment's reverse steps)."""
     import torch
 
     N = N or args.adj_steps
@@ -136,15 +145,20 @@ def run_adjoint(P, mask, args, N=None, K=None, g=None, label="grf_512"):
     nrev = N - 1
     if nrev > 0 and ph["reverse_ms"] > 0:
         rev_s = ph["reverse_ms"] * 1e-3 / nrev
-        ach = ADJ_ALG_BYTES * nf / rev_s / 1e9
+        segments = -(-nrev // K)
+        per_node = ADJ_ALG_BYTES - (ADJ_ACC_BYTES / 2) * segments / nrev   # mean over the launches
+        ach = per_node * nf / rev_s / 1e9
         out["reverse_step_us"] = rev_s * 1e6
         out["roofline"] = dict(bound="hbm", achieved=ach, peak=HBM_PEAK_GBS, unit="GB/s", frac=ach / HBM_PEAK_GBS,
-                               traffic=None, kernel="k_adjoint<BitmapIdx, false>",
-                               algorithmic_bytes_per_launch=ADJ_ALG_BYTES * nf)
+                               traffic=traffic_for(label, "adjoint", args.index),
+                               kernel="k_adjoint<BitmapIdx, false>",
+                               algorithmic_bytes_per_launch=per_node * nf,
+                               frac_population_bytes=ADJ_POP_BYTES * nf / rev_s / 1e9 / HBM_PEAK_GBS)
         both = (ph["reverse_ms"] + ph["recompute_ms"]) * 1e-3
-        ach2 = ADJ_RECOMPUTE_ALG_BYTES * nf * nrev / both / 1e9
+        sweep = per_node * nrev + 2 * 19 * 4 * (nrev - segments)   # bytes per node: reverse steps + recompute steps
+        ach2 = sweep * nf / both / 1e9
         out["roofline_with_recompute"] = dict(bound="hbm", achieved=ach2, peak=HBM_PEAK_GBS, unit="GB/s",
-                                              frac=ach2 / HBM_PEAK_GBS, bytes_per_node_step=ADJ_RECOMPUTE_ALG_BYTES)
+                                              frac=ach2 / HBM_PEAK_GBS, bytes_per_node_step=sweep / nrev)
     return out
 
 

@@ -363,7 +363,10 @@ int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int sto
         return fail(LBM_ERANGE, "the bitmap index holds rows of at most 4095 voxels");
     if (index_kind == LBM_INDEX_BITMAP && (int64_t)ny * nz * lbm::words_per_row(nx) >= ((int64_t)1 << 32))
         return fail(LBM_ERANGE, "the bitmap index holds fewer than 2^32 row words");
-    e = check_span(lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, kSlots), storage);
+    {
+        const lbm::NodeOrder o = lbm::node_order(geometry, nx, ny, nz);
+        e = check_span(lbm::gather_span(o.start, ny, nz, o.tile_z, kSlots), storage);
+    }
     if (!e.empty()) return fail(LBM_ERANGE, e);
     if (bytes) *bytes = layout(lbm::padded(nf), nf, storage, index_kind, nx, ny, nz).total;
     return LBM_OK;
@@ -528,7 +531,10 @@ int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, d
     c->steps = 0;
     c->field = nullptr;
     c->geom.assign(geometry, geometry + (size_t)nx * ny * nz);
-    c->span = lbm::gather_span(lbm::row_starts(geometry, nx, ny, nz), ny, nz, kSlots);
+    {
+        const lbm::NodeOrder o = lbm::node_order(geometry, nx, ny, nz);
+        c->span = lbm::gather_span(o.start, ny, nz, o.tile_z, kSlots);
+    }
     double gmax = std::max({std::fabs(g[0]), std::fabs(g[1]), std::fabs(g[2])});
     // FP16 scale: plain deviations hold the density deviation, which grows to
     // ~1e2-1e3 g in rock; the referenced ones hold velocity-sized values only

@@ -136,9 +136,11 @@ std::vector<int64_t> slab_offsets(const uint8_t* g, int nx, int ny, int nz) {
 }
 }  // namespace
 
-std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
+namespace {
+// Fluid voxels of every row r = z * ny + y.
+std::vector<int64_t> row_counts(const uint8_t* g, int nx, int ny, int nz) {
     const int64_t rows = (int64_t)ny * nz;
-    std::vector<int64_t> cnt(rows, 0), start(rows + 1, 0);
+    std::vector<int64_t> cnt(rows, 0);
     parallel_slabs(nz, rows * nx, [&](int z0, int z1) {
         for (int z = z0; z < z1; ++z)
             for (int y = 0; y < ny; ++y) {
@@ -148,12 +150,19 @@ std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
                 cnt[(int64_t)z * ny + y] = c;
             }
     });
+    return cnt;
+}
+
+// First node of every row in the order with z-tiles of tile_z planes.
+std::vector<int64_t> order_rows(const std::vector<int64_t>& cnt, int ny, int nz, int tile_z) {
+    const int64_t rows = (int64_t)ny * nz;
+    std::vector<int64_t> start(rows + 1, 0);
     int64_t n = 0;
-    const int T = (nz + kNodeTileZ - 1) / kNodeTileZ;
+    const int T = (nz + tile_z - 1) / tile_z;
     for (int p = 0; p < T; ++p) {
-        const int z0 = tile_at(p, T) * kNodeTileZ;
+        const int z0 = tile_at(p, T) * tile_z;
         for (int y = 0; y < ny; ++y)
-            for (int z = z0; z < std::min(nz, z0 + kNodeTileZ); ++z) {
+            for (int z = z0; z < std::min(nz, z0 + tile_z); ++z) {
                 const int64_t r = (int64_t)z * ny + y;
                 start[r] = n;
                 n += cnt[r];
@@ -163,12 +172,44 @@ std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
     return start;
 }
 
-GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz, int S) {
-    const int T = (nz + kNodeTileZ - 1) / kNodeTileZ;
+// The tallest of kNodeTileHeights whose gather span fits 32-bit byte offsets
+// with 4-byte elements, else with 2-byte ones, else the shortest.
+int tile_from_counts(const std::vector<int64_t>& cnt, int ny, int nz) {
+    for (const int elem : {4, 2})
+        for (const int h : kNodeTileHeights) {
+            const GatherSpan g = gather_span(order_rows(cnt, ny, nz, h), ny, nz, h, 19);
+            if ((double)(g.slack + g.reach) * elem < 4294967296.0 && g.slack < ((int64_t)1 << 32)) return h;
+        }
+    return 1;
+}
+}  // namespace
+
+int node_tile_z(const uint8_t* g, int nx, int ny, int nz) {
+    return tile_from_counts(row_counts(g, nx, ny, nz), ny, nz);
+}
+
+std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz, int tile_z) {
+    return order_rows(row_counts(g, nx, ny, nz), ny, nz, tile_z);
+}
+
+NodeOrder node_order(const uint8_t* g, int nx, int ny, int nz) {
+    const std::vector<int64_t> cnt = row_counts(g, nx, ny, nz);
+    NodeOrder o;
+    o.tile_z = tile_from_counts(cnt, ny, nz);
+    o.start = order_rows(cnt, ny, nz, o.tile_z);
+    return o;
+}
+
+std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz) {
+    return node_order(g, nx, ny, nz).start;
+}
+
+GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz, int tile_z, int S) {
+    const int T = (nz + tile_z - 1) / tile_z;
     const int64_t total = start[(int64_t)ny * nz];
     // first node of the tile at each position, and one past its last
     std::vector<int64_t> first(T), last(T);
-    for (int p = 0; p < T; ++p) first[p] = start[(int64_t)tile_at(p, T) * kNodeTileZ * ny];
+    for (int p = 0; p < T; ++p) first[p] = start[(int64_t)tile_at(p, T) * tile_z * ny];
     for (int p = 0; p < T; ++p) last[p] = p + 1 < T ? first[p + 1] : total;
     const int64_t E = (int64_t)S * kChunk;
     auto chunk_lo = [&](int64_t node) { return node / kChunk * E; };
@@ -199,10 +240,10 @@ CoordBits coord_bits(int nx, int ny, int nz) {
 }
 
 void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t stride,
-                 int32_t* table) {
+                 int32_t* table, int tile_z) {
     const int64_t plane = (int64_t)nx * ny, vol = plane * nz;
     std::vector<int32_t> node(vol);
-    auto start = row_starts(g, nx, ny, nz);
+    auto start = tile_z > 0 ? row_starts(g, nx, ny, nz, tile_z) : row_starts(g, nx, ny, nz);
     parallel_slabs(nz, vol, [&](int z0, int z1) {
         for (int z = z0; z < z1; ++z)
             for (int y = 0; y < ny; ++y) {

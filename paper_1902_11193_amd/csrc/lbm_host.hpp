@@ -35,21 +35,39 @@ struct CoordBits {
 CoordBits coord_bits(int nx, int ny, int nz);
 
 // Node order of the compacted fluid list: the (y, z) rows of the image are
-// taken in z-tiles of kNodeTileZ planes -- tile, then y, then z inside the
-// tile -- and the fluid voxels of each row in increasing x.  Rows that are
-// neighbours in y or z then sit at most kNodeTileZ rows apart in the list
-// (except across tile faces), so the cache lines a step gathers from are
-// reused while still in L2.  The tiles themselves are folded: tile t of T
-// comes at position 2t when 2t < T, else at 2(T - 1 - t) + 1 (order 0, T-1,
-// 1, T-2, ...), so tiles that touch in z, across the periodic wrap too, are
-// at most two positions apart and every gather stays near its node.
-constexpr int kNodeTileZ = 16;
+// taken in z-tiles of tile_z planes -- tile, then y, then z inside the tile --
+// and the fluid voxels of each row in increasing x.  Rows that are neighbours
+// in y or z then sit at most tile_z rows apart in the list (except across
+// tile faces).  The tiles themselves are folded: tile t of T comes at
+// position 2t when 2t < T, else at 2(T - 1 - t) + 1 (order 0, T-1, 1, T-2,
+// ...), so tiles that touch in z, across the periodic wrap too, are at most
+// two positions apart and every gather stays near its node.
+//
+// The gathers across a tile face reach a tile two positions away, whose lines
+// no cache still holds, and the same lines are fetched again when that tile
+// is stepped; within a tile a neighbour row tile_z rows back was fetched
+// moments before (by another XCD, possibly, from the MALL).  So the tiles are
+// as tall as the 32-bit gather offsets allow: node_tile_z takes the tallest
+// height of kNodeTileHeights whose gather span fits with 4-byte elements
+// (else with 2-byte ones).  (512^3 rock, FP32 storage: 0.767 ms per step with
+// 16-plane tiles, 0.745 with 64, 0.738 with 96 or 128; the 16-bit storages
+// within 0.5%.)  The choice depends on the image alone, so every storage and
+// every call that orders the nodes agrees on it.
+constexpr int kNodeTileHeights[] = {128, 64, 32, 16, 8, 4, 2, 1};
 inline int tile_at(int p, int T) { return (p & 1) ? T - 1 - (p >> 1) : (p >> 1); }
 inline int tile_pos(int t, int T) { return 2 * t < T ? 2 * t : 2 * (T - 1 - t) + 1; }
+int node_tile_z(const uint8_t* geom, int nx, int ny, int nz);
 
 // Node number of the first fluid voxel of every row r = z * ny + y
-// (entry ny * nz holds the fluid count).
+// (entry ny * nz holds the fluid count), in the image's order (node_tile_z),
+// or with the given tile height.
 std::vector<int64_t> row_starts(const uint8_t* geom, int nx, int ny, int nz);
+std::vector<int64_t> row_starts(const uint8_t* geom, int nx, int ny, int nz, int tile_z);
+struct NodeOrder {
+    int tile_z;
+    std::vector<int64_t> start;  // row_starts with that height
+};
+NodeOrder node_order(const uint8_t* geom, int nx, int ny, int nz);
 
 // Padded node count: the fluid list rounded up to a multiple of kChunk.
 constexpr int kChunk = 256;
@@ -64,17 +82,18 @@ inline int64_t state_elem(int i, int64_t n, int S = 19) {
 
 // The step kernels address a chunk's gathers as 32-bit byte offsets from a
 // base `slack` elements below the chunk.  From the tile structure of the node
-// order (row_starts), gather_span bounds how far below its chunk (slack) and
+// order (row_starts with tile height tile_z), gather_span bounds how far below its chunk (slack) and
 // how far past its start (reach) a chunk's gathered elements can lie; the
 // offsets fit when (slack + reach) * element size < 2^32.
 struct GatherSpan {
     int64_t slack, reach;  // elements
 };
-GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz, int S = 19);
+GatherSpan gather_span(const std::vector<int64_t>& start, int ny, int nz, int tile_z, int S = 19);
 
-// Pull-source table [18][stride], entry (i-1)*stride + n; -1 = solid source.
+// Pull-source table [18][stride], entry (i-1)*stride + n; -1 = solid source;
+// nodes in the image's order, or with tiles of tile_z planes when tile_z > 0.
 void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_t stride,
-                 int32_t* table);
+                 int32_t* table, int tile_z = 0);
 
 // Bitmap index.  Every (y, z) row of the image is a padded bit string of
 // nx + 2 positions: position x + 1 holds voxel x, position 0 repeats voxel

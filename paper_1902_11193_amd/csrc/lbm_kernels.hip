@@ -1106,7 +1106,9 @@ __device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w
 // The body-force sensitivity of the node is added to an FP32 accumulator
 // [3][stride] (written, not added, when `first`: the first reverse step of a
 // checkpoint segment); the host folds it into the FP64 total once per segment,
-// so an FP32 sum runs over at most one segment.  Software pipeline as in
+// so an FP32 sum runs over at most one segment.  Each accumulator value is
+// touched once per step, so it is read and written with non-temporal
+// accesses that leave L2 to the gathered lines.  Software pipeline as in
 // k_step: the index records of the next node are loaded and decoded while
 // this node's 38 gathers are in flight.  It is launched with one block per
 // compute unit (its two gathered arrays make it bound by L2 misses, not by
@@ -1152,9 +1154,9 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
             const uint32_t e = c * kThreads + threadIdx.x;   // this lane's slot
             float d[3] = {0.f, 0.f, 0.f};
             if (!first) {
-                d[0] = dkdF[e];
-                d[1] = dkdF[stride + e];
-                d[2] = dkdF[2 * stride + e];
+                d[0] = __builtin_nontemporal_load(dkdF + e);
+                d[1] = __builtin_nontemporal_load(dkdF + stride + e);
+                d[2] = __builtin_nontemporal_load(dkdF + 2 * stride + e);
             }
             float Fx = Fx0, Fy = Fy0, Fz = Fz0;
             if (FIELD) {
@@ -1254,9 +1256,9 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
             d[0] += 0.5f * nu.jx + gjd.x + tq * gq * mu.qx + mu.jx;
             d[1] += 0.5f * nu.jy + gjd.y + tq * gq * mu.qy + mu.jy;
             d[2] += 0.5f * nu.jz + gjd.z + tq * gq * mu.qz + mu.jz;
-            dkdF[e] = d[0];
-            dkdF[stride + e] = d[1];
-            dkdF[2 * stride + e] = d[2];
+            __builtin_nontemporal_store(d[0], dkdF + e);
+            __builtin_nontemporal_store(d[1], dkdF + stride + e);
+            __builtin_nontemporal_store(d[2], dkdF + 2 * stride + e);
             add_back(b, nu);
             float* ob_ = aout + (size_t)c * kChunkElems;
             unroll<19>([&](auto k) {

@@ -1,5 +1,6 @@
 // Brute-force check of the chunked population layout and its gather span on
-// random periodic images: every element a node's step touches (pull sources,
+// random periodic images, for the tile height the image gets and for fixed
+// ones: every element a node's step touches (pull sources,
 // bounce-back own populations, own stores) must lie inside the population
 // array and within [chunk_base - slack, chunk_base + reach) of its chunk, and
 // the node order must be a permutation of the fluid voxels.  Exit status 0
@@ -22,11 +23,12 @@ int main() {
         if (nf == 0) continue;
         ++cases;
         int64_t np = padded(nf);
-        std::vector<int32_t> t((size_t)18 * np, -1);
-        build_table(g.data(), nx, ny, nz, nf, np, t.data());
-        auto st = row_starts(g.data(), nx, ny, nz);
+        for (int tz : {node_tile_z(g.data(), nx, ny, nz), 1, 2, 3, 16})  // the image's height and fixed ones
         for (int S : {19, 20}) {  // 19 populations, or 20 values with a reference-density slot
-            GatherSpan sp = gather_span(st, ny, nz, S);
+            std::vector<int32_t> t((size_t)18 * np, -1);
+            build_table(g.data(), nx, ny, nz, nf, np, t.data(), tz);
+            auto st = row_starts(g.data(), nx, ny, nz, tz);
+            GatherSpan sp = gather_span(st, ny, nz, tz, S);
             const int64_t E = (int64_t)S * kChunk;
             for (int64_t n = 0; n < nf; ++n) {
                 int64_t cb = (n / kChunk) * E;
@@ -54,6 +56,20 @@ int main() {
         fluid_voxels(g.data(), nx, ny, nz, vox.data());
         std::vector<char> seen((size_t)nx * ny * nz, 0);
         for (auto v : vox) { if (g[v] != 0 || seen[v]) { ++bad; } seen[v] = 1; }
+    }
+    // The tile height of an image is the tallest candidate whose span fits
+    // 32-bit byte offsets with 4-byte elements: on a fully fluid 512^3 box
+    // (134 M nodes) 32 planes fit and 64 do not.
+    {
+        const int n = 512;
+        std::vector<uint8_t> g((size_t)n * n * n, 0);
+        const int tz = node_tile_z(g.data(), n, n, n);
+        auto fits = [&](int h) {
+            GatherSpan sp = gather_span(row_starts(g.data(), n, n, n, h), n, n, h, 19);
+            return (double)(sp.slack + sp.reach) * 4 < 4294967296.0;
+        };
+        printf("512^3 fluid box: tile height %d\n", tz);
+        if (tz != 32 || !fits(32) || fits(64)) ++bad;
     }
     printf("cases %d bad %d\n", cases, bad);
     return bad != 0;

@@ -79,9 +79,11 @@ def test_rates_reject():
         assert e.value.code == P.LBM_EINVAL
 
 
-def _brute_node_order(mask, tile=16):
+def _brute_node_order(mask, tile=128):
     """Fluid voxels sorted by (position of the z-tile, y, z % tile, x), where the
-    tiles t = z // tile of T are folded into the order 0, T-1, 1, T-2, ..."""
+    tiles t = z // tile of T are folded into the order 0, T-1, 1, T-2, ...
+    An image whose gathers span less than 2^32 bytes around every chunk with
+    128-plane tiles (every image of these tests) gets tiles of 128 planes."""
     nz, ny, nx = mask.shape
     T = -(-nz // tile)
     t = np.arange(T)
@@ -128,7 +130,8 @@ def test_neighbor_table_brute_force_and_permutation(shape, sf, seed):
     assert (reads == 1).all()
 
 
-@pytest.mark.parametrize("shape", [(5, 6, 7), (40, 3, 9), (33, 17, 2), (64, 2, 3), (70, 3, 4)])
+@pytest.mark.parametrize("shape", [(5, 6, 7), (40, 3, 9), (33, 17, 2), (64, 2, 3), (70, 3, 4), (300, 2, 3),
+                                   (390, 3, 2), (129, 2, 2)])
 def test_node_order_is_z_tiled_rows(shape):
     mask = random_mask(shape, 0.3, 4)
     order = P.lbm_node_order(mask)
