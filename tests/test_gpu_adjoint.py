@@ -43,6 +43,13 @@ def test_adjoint_matches_oracle_small(rset, tau, Lam):
     _compare(mask, rset, tau, Lam, (1e-5, 2e-6, -1e-6), N=40, K=7)
 
 
+def test_adjoint_three_z_tiles_matches_oracle():
+    """300 planes: three 128-plane z-tiles in folded order, so the transposed
+    gathers cross every tile face and the periodic z wrap."""
+    mask = percolating_x(random_mask((300, 4, 5), 0.25, seed=33))
+    _compare(mask, "E", 0.9, 3 / 16, (1e-5, 2e-6, -1e-6), N=30, K=7)
+
+
 def test_adjoint_table_layout_and_single_segment():
     mask = percolating_x(random_mask((6, 7, 9), 0.25, seed=32))
     _compare(mask, "D", 1.0, None, (1e-5, 0, 0), N=25, K=100, index="table")

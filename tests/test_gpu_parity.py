@@ -25,6 +25,8 @@ CASES = [
     ("rand_ragged", lambda: random_mask((7, 9, 11), 0.35, 12)),
     ("rows130", lambda: random_mask((2, 3, 130), 0.25, 13)),
     ("sphere16", lambda: sphere(16, (7.5, 7.5, 7.5), 4.0)),
+    # 300 planes: three 128-plane z-tiles in folded order, gathers across every tile face and the z wrap
+    ("tiles300", lambda: random_mask((300, 3, 4), 0.3, 14)),
 ]
 G = (1e-4, 5e-5, -2e-5)
 
@@ -63,11 +65,13 @@ def test_populations_match_oracle(name, make, index):
 
 
 @pytest.mark.parametrize("shape,solid", [((9, 10, 70), 0.3), ((5, 3, 18), 0.3), ((4, 7, 19), 0.2),
-                                         ((6, 4, 37), 0.4), ((3, 1, 36), 0.1), ((3, 2, 4095), 0.05)])
+                                         ((6, 4, 37), 0.4), ((3, 1, 36), 0.1), ((3, 2, 4095), 0.05),
+                                         ((260, 4, 5), 0.3)])
 def test_table_and_bitmap_bitwise_equal(shape, solid):
     """The bitmap index reaches the same pull sources as the table: states and
     histories agree bit for bit, for row lengths around the bitmap's 18-voxel
-    word step, a single-row-per-plane image and the longest rows it holds."""
+    word step, a single-row-per-plane image, the longest rows it holds and
+    three z-tiles (260 planes)."""
     mask = random_mask(shape, solid, 5)
     banner(f"table vs bitmap {shape}")
     states = []
