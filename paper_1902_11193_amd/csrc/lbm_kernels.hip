@@ -729,23 +729,27 @@ __device__ __forceinline__ void zou_he(float f[19], uint32_t side, float drho_in
     const float H0 = f[0] + (f[3] + f[4]) + (f[5] + f[6]) + (f[15] + f[16]) + (f[17] + f[18]);
     const float Ny = 0.5f * ((f[3] - f[4]) + (f[15] - f[16]) + (f[17] - f[18]));
     const float Nz = 0.5f * ((f[5] - f[6]) + (f[15] - f[16]) - (f[17] - f[18]));
-    if (side == 1u) {
-        const float ju = drho_in - (H0 + 2.f * (f[2] + f[8] + f[10] + f[12] + f[14]));
-        const float j3 = ju * (1.f / 3.f), j6 = ju * (1.f / 6.f);
-        f[1] = f[2] + j3;
-        f[7] = f[8] + j6 - Ny;
-        f[9] = f[10] + j6 + Ny;
-        f[11] = f[12] + j6 - Nz;
-        f[13] = f[14] + j6 + Nz;
-    } else {
-        const float ju = (H0 + 2.f * (f[1] + f[7] + f[9] + f[11] + f[13])) - drho_out;
-        const float j3 = ju * (1.f / 3.f), j6 = ju * (1.f / 6.f);
-        f[2] = f[1] - j3;
-        f[8] = f[7] - j6 + Ny;
-        f[10] = f[9] - j6 - Ny;
-        f[12] = f[11] - j6 + Nz;
-        f[14] = f[13] - j6 - Nz;
-    }
+    // Both faces' values, then selects: with two branches that store to
+    // different elements the compiler turned f into a stack array.
+    const bool in = side == 1u;
+    const float ju_in = drho_in - (H0 + 2.f * (f[2] + f[8] + f[10] + f[12] + f[14]));
+    const float ju_out = (H0 + 2.f * (f[1] + f[7] + f[9] + f[11] + f[13])) - drho_out;
+    const float ju = in ? ju_in : ju_out;
+    const float j3 = ju * (1.f / 3.f), j6 = ju * (1.f / 6.f);
+    const float a1 = f[2] + j3, a7 = f[8] + j6 - Ny, a9 = f[10] + j6 + Ny, a11 = f[12] + j6 - Nz,
+                a13 = f[14] + j6 + Nz;
+    const float b2 = f[1] - j3, b8 = f[7] - j6 + Ny, b10 = f[9] - j6 - Ny, b12 = f[11] - j6 + Nz,
+                b14 = f[13] - j6 - Nz;
+    f[1] = in ? a1 : f[1];
+    f[7] = in ? a7 : f[7];
+    f[9] = in ? a9 : f[9];
+    f[11] = in ? a11 : f[11];
+    f[13] = in ? a13 : f[13];
+    f[2] = in ? f[2] : b2;
+    f[8] = in ? f[8] : b8;
+    f[10] = in ? f[10] : b10;
+    f[12] = in ? f[12] : b12;
+    f[14] = in ? f[14] : b14;
 }
 
 // ------------------------------------------------------------------ TRT
