@@ -832,10 +832,12 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out) {
 // chunks away in the node order, so most of its gathers hit the L2 of the XCD
 // that reads them, while all XCDs still work inside one window of the node
 // list and share the MALL and the DRAM pages it covers.  (Measured on a 512^3
-// rock: runs of 16-32 chunks +3% FP32 over plain round-robin, runs of 64
-// equal, 128 -3%; a contiguous eighth of the list per XCD -6%.)  A grid that
-// is not a multiple of 8 kXcdRun keeps plain round-robin.  The map is a
-// bijection of [0, G).
+// rock at 5 blocks per CU: runs of 16-32 chunks +3% FP32 over plain
+// round-robin, runs of 64 equal, 128 -3%; a contiguous eighth of the list per
+// XCD -6%.  At one block per CU, where 256 blocks make runs of 32 the whole
+// window of each XCD: plain round-robin -4%, bands of 2 to 16 windows per
+// XCD -2% to -10%.)  A grid that is not a multiple of 8 kXcdRun keeps
+// plain round-robin.  The map is a bijection of [0, G).
 constexpr uint32_t kXcdRun = 32;
 __device__ __forceinline__ uint32_t logical_block() {
     const uint32_t G = gridDim.x, b = blockIdx.x;
@@ -894,9 +896,10 @@ k_finalize_ring(const double* __restrict__ partials, int grid, double* __restric
 // ZH: Zou-He pressure boundaries on the x faces (bitmap index only, which
 // knows each node's x).  SYM: symmetry planes on the y / z faces (bitmap
 // index, BitmapIdx::offsets).
-// The plain MRT step fits 96 VGPRs without spilling and then runs 5 waves per
-// SIMD (+0.8% FP32 on a 512^3 rock); the reference-density, link-wise TRT and
-// full-way variants would spill there and keep the compiler's choice.
+// The plain MRT step fits 96 VGPRs without spilling, so 5 blocks of it fit a
+// CU, which the 16-bit storages use (FP32 storage launches one block per CU);
+// the reference-density, link-wise TRT, full-way and symmetry variants would
+// spill there and keep the compiler's choice.
 template <class C, class Ix, bool FIELD, bool TRT, bool FW, bool ZH = false, bool SYM = false>
 __global__ void __launch_bounds__(kThreads, (C::kRef || TRT || FW || SYM) ? 1 : 5)
 k_step(const typename C::T* __restrict__ src, typename C::T* __restrict__ dst, Ix ix,
