@@ -259,8 +259,8 @@ def main():
     ap.add_argument("--tau", type=float, default=1.0)
     ap.add_argument("--Lambda", type=float, default=3 / 16)
     ap.add_argument("--g", type=float, default=None)
-    ap.add_argument("--adj-steps", type=int, default=100)
-    ap.add_argument("--adj-checkpoint", type=int, default=10)
+    ap.add_argument("--adj-steps", type=int, default=400)
+    ap.add_argument("--adj-checkpoint", type=int, default=20)
     ap.add_argument("--cpu-crop", type=int, default=128)
     ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
