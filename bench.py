@@ -277,7 +277,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the solver has no multi-GPU path "
               "(the domain would split into x-slabs with halo exchange; not built)", file=sys.stderr)
         sys.exit(2)
 

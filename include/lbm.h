@@ -360,7 +360,7 @@ int lbm_set_graphs(lbm_ctx* ctx, int enable);
  * BF16 storage, where e = 0. */
 int lbm_set_storage_exponent(lbm_ctx* ctx, int e);
 
-/* Discrete adjoint (spec extension of the paper's method): exact
+/* Discrete adjoint (an extension beyond the paper's method): exact
  * derivatives of k_N (the permeability after N = n_steps steps from rest,
  * along the largest |g| component) with respect to tau, Lambda and the
  * per-node body-force acceleration, by reverse time stepping with

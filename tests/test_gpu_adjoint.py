@@ -2,8 +2,8 @@
 central finite differences), plus properties at full size.
 
 Tolerance: the GPU adjoint runs in FP32 with FP64 accumulation; gradients must
-agree with the FP64 oracle to 1e-4 of their scale (the benchmark spec's bound for
-the adjoint against finite differences)."""
+agree with the FP64 oracle to 1e-4 of their scale (the bound the adjoint is
+held to against finite differences)."""
 import numpy as np
 import pytest
 import torch

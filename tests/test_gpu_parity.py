@@ -189,11 +189,15 @@ def test_run_to_steady_matches_oracle_step_count():
 
 
 def _record(name, **kw):
-    """Append a measurement to gpurun_out/storage_accuracy.jsonl (kept with the run's output)."""
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    os.makedirs(out, exist_ok=True)
-    with open(os.path.join(out, "storage_accuracy.jsonl"), "a") as fh:
-        fh.write(json.dumps(dict(case=name, **kw)) + "\n")
+    """Print a measurement, and append it to storage_accuracy.jsonl in the
+    directory LBM_RECORD_DIR names, when it is set."""
+    line = json.dumps(dict(case=name, **kw))
+    print(line)
+    out = os.environ.get("LBM_RECORD_DIR")
+    if out:
+        os.makedirs(out, exist_ok=True)
+        with open(os.path.join(out, "storage_accuracy.jsonl"), "a") as fh:
+            fh.write(line + "\n")
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16r", "f16", "bf16"])
