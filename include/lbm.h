@@ -16,10 +16,13 @@
  *     solid.  The box is periodic in all three axes.
  *   - Only fluid voxels carry populations.  They are numbered 0..n_fluid-1,
  *     the "compacted fluid list", in node order: the (y, z) rows of the image
- *     taken in z-tiles of 16 planes (tile, then y, then z inside the tile),
- *     the fluid voxels of each row in increasing x.  The T = ceil(nz / 16)
+ *     taken in z-tiles of h planes (tile, then y, then z inside the tile),
+ *     the fluid voxels of each row in increasing x.  The T = ceil(nz / h)
  *     tiles come folded, t = 0, T-1, 1, T-2, ..., so tiles that touch in z
- *     (periodic wrap included) are near each other in the list.  Every per-node
+ *     (periodic wrap included) are near each other in the list.  h is the
+ *     tallest of 128, 64, 32, ..., 1 planes for which the populations
+ *     gathered around any 256-node chunk span less than 4 GiB in FP32 (else
+ *     in a 16-bit storage); it depends on the image alone.  Every per-node
  *     array of this interface (state, force field, gradients, neighbour
  *     table) uses this order; lbm_node_order gives the voxel of each node.
  *   - Velocity order i = 0..18 (pairs i, i+1 for odd i are opposite):
@@ -148,8 +151,9 @@ int lbm_rates(int relaxation_set, double tau, double Lambda, double s[19],
  * LBM_ERANGE: 2^31 or more fluid nodes; with the bitmap index, packed
  * coordinates over 32 bits, nx above 4095 or 2^32 row words or more; or the
  * populations gathered around one 256-node chunk
- * spanning 4 GiB or more in the chosen storage (three 16-plane z-tiles of
- * fluid nodes at 76 bytes each for FP32, 38 for FP16/BF16/F16R). */
+ * spanning 4 GiB or more in the chosen storage (up to five z-tiles of fluid
+ * nodes, with the tile height of the node order, at 76 bytes each for FP32,
+ * 38 for FP16/BF16/F16R). */
 int lbm_workspace_query(const uint8_t* geometry, int nx, int ny, int nz, int storage,
                         int index_kind, size_t* bytes, int64_t* n_fluid);
 
