@@ -101,14 +101,17 @@ extern "C" {
  * LBM_INDEX_TABLE:  int32 [18][n_pad] table of pull-source nodes (-1 = wall),
  *                   72 bytes per fluid node.
  * LBM_INDEX_BITMAP: one packed uint32 voxel coordinate per node plus, for
- *                   every (y, z) row and every 18 voxels of it, an 8-byte
- *                   record (20 fluid bits, the row's fluid count, the node
- *                   number before them), kept side by side with the records
- *                   of rows y - 1 and y + 1 of the same plane; the source node
- *                   of a link is found by a population count.  4 bytes per
- *                   node + 1.33 bytes per voxel.  Needs ceil(log2 nx) +
- *                   ceil(log2 ny) + ceil(log2 nz) <= 32, nx <= 4095 and fewer
- *                   than 2^32 row words (ny nz ceil(nx / 18)). */
+ *                   every (y, z) row and every 18 voxels of it, a 16-byte
+ *                   entry (the 20 fluid bits of that word in rows y - 1, y,
+ *                   y + 1 of the plane, the node number before the word in
+ *                   row y and the differences to those of rows y - 1 and
+ *                   y + 1) and that node number again (for the rows across
+ *                   the periodic y wrap), and each row's fluid count; the
+ *                   source node of a link is found by a population count.
+ *                   4 bytes per node + 1.12 bytes per voxel.  Needs
+ *                   ceil(log2 nx) + ceil(log2 ny) + ceil(log2 nz) <= 32,
+ *                   nx <= 4095 and fewer than 2^32 row words
+ *                   (ny nz ceil(nx / 18)). */
 #define LBM_INDEX_TABLE 0
 #define LBM_INDEX_BITMAP 1
 
@@ -343,8 +346,8 @@ int lbm_set_pressure(lbm_ctx* ctx, int enable, double rho_in, double rho_out);
  * half a voxel outside the layer).  Halfway (or full-way) bounce-back applies
  * where that voxel is solid.  The same problem as lbm_boundary_image's
  * reflected image, without its 2x (4x) nodes.  Needs the bitmap index and
- * FP32 storage, no pressure faces (else LBM_EINVAL); rebuilds the row
- * records (synchronises the stream).  (0, 0) returns to the periodic box.
+ * FP32 storage, no pressure faces (else LBM_EINVAL); rebuilds the index
+ * entries (synchronises the stream).  (0, 0) returns to the periodic box.
  * lbm_adjoint refuses a context with symmetry planes. */
 int lbm_set_symmetry(lbm_ctx* ctx, int mirror_y, int mirror_z);
 

@@ -56,7 +56,7 @@ size_t state_bytes(int storage, int64_t np) {
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
-    size_t A, B, table, coords, rec, partials, ring, total;
+    size_t A, B, table, coords, ent, base, count, partials, ring, total;
 };
 
 Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int ny, int nz) {
@@ -71,11 +71,15 @@ Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int n
         L.table = off;
         off += align256((size_t)18 * np * 4);
     } else {
-        const size_t recs = (size_t)ny * nz * lbm::words_per_row(nx) * 3;
+        const size_t words = (size_t)ny * nz * lbm::words_per_row(nx);
         L.coords = off;
         off += align256((size_t)std::max<int64_t>(nf, 1) * 4);
-        L.rec = off;
-        off += align256(recs * sizeof(lbm::RowRec));
+        L.ent = off;
+        off += align256(words * 16);
+        L.base = off;
+        off += align256(words * 4);
+        L.count = off;
+        off += align256((size_t)ny * nz * 4);
     }
     // the reduction scratch, kReductionBytes at the end (lbm_setup_static
     // contexts keep it in the static array instead)
@@ -581,8 +585,12 @@ int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, d
                             hipMemcpyHostToDevice, c->stream);
     } else {
         lbm::build_bitmap(geometry, nx, ny, nz, nf, &bm);
+        if (!bm.fits)
+            return cleanup(fail(LBM_ERANGE, "the bitmap index's row-base differences exceed 18 bits"));
         v.coords = reinterpret_cast<const uint32_t*>(c->ws + c->L.coords);
-        v.rec = c->ws + c->L.rec;
+        v.ent = c->ws + c->L.ent;
+        v.base = reinterpret_cast<const int32_t*>(c->ws + c->L.base);
+        v.count = reinterpret_cast<const uint32_t*>(c->ws + c->L.count);
         v.nx = nx;
         v.ny = ny;
         v.nz = nz;
@@ -592,8 +600,14 @@ int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, d
         he = hipMemcpyAsync(c->ws + c->L.coords, bm.coords.data(), bm.coords.size() * 4,
                             hipMemcpyHostToDevice, c->stream);
         if (he == hipSuccess)
-            he = hipMemcpyAsync(c->ws + c->L.rec, bm.rec.data(), bm.rec.size() * sizeof(lbm::RowRec),
-                                hipMemcpyHostToDevice, c->stream);
+            he = hipMemcpyAsync(c->ws + c->L.ent, bm.ent.data(), bm.ent.size() * 4, hipMemcpyHostToDevice,
+                                c->stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(c->ws + c->L.base, bm.base.data(), bm.base.size() * 4, hipMemcpyHostToDevice,
+                                c->stream);
+        if (he == hipSuccess)
+            he = hipMemcpyAsync(c->ws + c->L.count, bm.count.data(), bm.count.size() * 4, hipMemcpyHostToDevice,
+                                c->stream);
     }
     if (he == hipSuccess) he = lbm::launch_zero(c->ws + c->L.A, (int64_t)(c->L.B - c->L.A) * 2, c->stream);
     if (he == hipSuccess) he = zero_ring(c);
@@ -939,12 +953,13 @@ int lbm_set_symmetry(lbm_ctx* c, int mirror_y, int mirror_z) {
     if (sym && c->storage != LBM_F32) return fail(LBM_EINVAL, "symmetry planes need FP32 storage");
     if (sym && c->pressure) return fail(LBM_EINVAL, "symmetry planes cannot be combined with pressure faces");
     if (sym == c->idx.sym) return LBM_OK;
-    // the records hold ghost rows beyond mirrored y faces (the z ghost planes
-    // are chosen in the kernel)
+    // the entries hold ghost rows beyond mirrored y faces (the z ghost planes
+    // are chosen in the kernel); the bases and counts do not change
     lbm::BitmapIndex bm;
     lbm::build_bitmap(c->geom.data(), c->nx, c->ny, c->nz, c->nf, &bm, (sym & 1) != 0);
-    HIP_TRY(hipMemcpyAsync(c->ws + c->L.rec, bm.rec.data(), bm.rec.size() * sizeof(lbm::RowRec),
-                           hipMemcpyHostToDevice, c->stream));
+    if (!bm.fits) return fail(LBM_ERANGE, "the bitmap index's row-base differences exceed 18 bits");
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.ent, bm.ent.data(), bm.ent.size() * 4, hipMemcpyHostToDevice,
+                           c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->idx.sym = sym;
     drop_graphs(c);

@@ -4,6 +4,7 @@
 #include "lbm_host.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <thread>
@@ -173,10 +174,14 @@ std::vector<int64_t> order_rows(const std::vector<int64_t>& cnt, int ny, int nz,
 }
 
 // The tallest of kNodeTileHeights whose gather span fits 32-bit byte offsets
-// with 4-byte elements, else with 2-byte ones, else the shortest.
-int tile_from_counts(const std::vector<int64_t>& cnt, int ny, int nz) {
+// with 4-byte elements, else with 2-byte ones, else the shortest; and whose
+// rows y - 1, y + 1 stay close enough for the bitmap index's base
+// differences: (h + 1) nx + 1 < 2^(kDeltaBits - 1).
+int tile_from_counts(const std::vector<int64_t>& cnt, int nx, int ny, int nz) {
+    const int64_t lim = (int64_t)1 << (kDeltaBits - 1);
     for (const int elem : {4, 2})
         for (const int h : kNodeTileHeights) {
+            if (((int64_t)std::min(h, nz) + 1) * nx + 1 >= lim) continue;
             const GatherSpan g = gather_span(order_rows(cnt, ny, nz, h), ny, nz, h, 19);
             if ((double)(g.slack + g.reach) * elem < 4294967296.0 && g.slack < ((int64_t)1 << 32)) return h;
         }
@@ -185,7 +190,7 @@ int tile_from_counts(const std::vector<int64_t>& cnt, int ny, int nz) {
 }  // namespace
 
 int node_tile_z(const uint8_t* g, int nx, int ny, int nz) {
-    return tile_from_counts(row_counts(g, nx, ny, nz), ny, nz);
+    return tile_from_counts(row_counts(g, nx, ny, nz), nx, ny, nz);
 }
 
 std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz, int tile_z) {
@@ -195,7 +200,7 @@ std::vector<int64_t> row_starts(const uint8_t* g, int nx, int ny, int nz, int ti
 NodeOrder node_order(const uint8_t* g, int nx, int ny, int nz) {
     const std::vector<int64_t> cnt = row_counts(g, nx, ny, nz);
     NodeOrder o;
-    o.tile_z = tile_from_counts(cnt, ny, nz);
+    o.tile_z = tile_from_counts(cnt, nx, ny, nz);
     o.start = order_rows(cnt, ny, nz, o.tile_z);
     return o;
 }
@@ -275,13 +280,18 @@ void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t s
 
 void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out, bool mirror_y) {
     const int W = words_per_row(nx);
+    const int64_t rows = (int64_t)ny * nz;
     out->words = W;
     out->bits = coord_bits(nx, ny, nz);
     out->coords.assign(nf, 0);
-    out->rec.assign((size_t)nz * ny * W * 3, RowRec{0, 0});
+    out->ent.assign((size_t)rows * W * 4, 0u);
+    out->base.assign((size_t)rows * W, 0);
+    out->count.assign((size_t)rows, 0u);
+    std::vector<uint32_t> bits_of((size_t)rows * W, 0u);
     auto start = row_starts(g, nx, ny, nz);
     const int bx = out->bits.bx, by = out->bits.by;
-    parallel_slabs(nz, (int64_t)ny * nz * nx, [&](int z0, int z1) {
+    // every row word's bits and base, every row's count, every node's coordinate
+    parallel_slabs(nz, rows * nx, [&](int z0, int z1) {
         std::vector<uint8_t> pad(nx + 2);
         for (int z = z0; z < z1; ++z)
             for (int y = 0; y < ny; ++y) {
@@ -294,6 +304,7 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                 pad[nx + 1] = pad[1];
                 uint32_t count = 0;
                 for (int x = 0; x < nx; ++x) count += pad[x + 1];
+                out->count[r] = count;
                 int64_t before = 0;  // fluid voxels at real positions [1, kWordStep w)
                 for (int w = 0; w < W; ++w) {
                     uint32_t bits = 0;
@@ -301,21 +312,8 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                         const int q = kWordStep * w + b;
                         if (q < nx + 2 && pad[q]) bits |= 1u << b;
                     }
-                    const int64_t base = rowstart + before - (w == 0 ? pad[0] : 0);
-                    const RowRec rr{bits | count << 20, (int32_t)base};
-                    // this row is row y of its own triple, row y + 1 of row
-                    // y - 1's and row y - 1 of row y + 1's (periodic in y; with
-                    // ny <= 2 one triple takes it in two or three slots).  With
-                    // symmetry planes on the y faces the rows beyond them are
-                    // the ghost images of the boundary rows: row 0 is its own
-                    // row y - 1 and row ny - 1 its own row y + 1.
-                    int yn[3] = {(y + 1) % ny, y, (y + ny - 1) % ny};
-                    if (mirror_y && y == ny - 1) yn[0] = -1;
-                    if (mirror_y && y == 0) yn[2] = -1;
-                    for (int k = 0; k < 3; ++k)
-                        if (yn[k] >= 0) out->rec[(((int64_t)z * ny + yn[k]) * W + w) * 3 + k] = rr;
-                    if (mirror_y && y == 0) out->rec[(((int64_t)z * ny + y) * W + w) * 3 + 0] = rr;
-                    if (mirror_y && y == ny - 1) out->rec[(((int64_t)z * ny + y) * W + w) * 3 + 2] = rr;
+                    bits_of[r * W + w] = bits;
+                    out->base[r * W + w] = (int32_t)(rowstart + before - (w == 0 ? pad[0] : 0));
                     for (int b = 0; b < kWordStep; ++b) {
                         const int q = kWordStep * w + b;
                         if (q >= 1 && q <= nx) before += pad[q];
@@ -327,6 +325,34 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                             (uint32_t)x | ((uint32_t)y << bx) | ((uint32_t)z << (bx + by));
             }
     });
+    // the entries: rows y - 1 and y + 1 periodic in y, or, with symmetry
+    // planes on the y faces, row 0 its own row y - 1 and row ny - 1 its own
+    // row y + 1 (their ghost images); across the periodic wrap the kernel
+    // reads the base from `base` and the difference is left 0
+    const int64_t lim = (int64_t)1 << (kDeltaBits - 1);
+    std::atomic<bool> fits{true};
+    parallel_slabs(nz, rows * W, [&](int z0, int z1) {
+        for (int z = z0; z < z1; ++z)
+            for (int y = 0; y < ny; ++y) {
+                const int ym = y == 0 ? (mirror_y ? 0 : ny - 1) : y - 1;
+                const int yp = y == ny - 1 ? (mirror_y ? ny - 1 : 0) : y + 1;
+                const bool wm = ny > 1 && !mirror_y && y == 0, wp = ny > 1 && !mirror_y && y == ny - 1;
+                const int64_t r = (int64_t)z * ny + y, rm = (int64_t)z * ny + ym, rp = (int64_t)z * ny + yp;
+                for (int w = 0; w < W; ++w) {
+                    const int64_t b0 = out->base[r * W + w];
+                    const int64_t dm = wm ? 0 : out->base[rm * W + w] - b0;
+                    const int64_t dp = wp ? 0 : out->base[rp * W + w] - b0;
+                    if (dm < -lim || dm >= lim || dp < -lim || dp >= lim) fits = false;
+                    const uint32_t um = (uint32_t)dm, up = (uint32_t)dp;
+                    uint32_t* e = &out->ent[(size_t)(r * W + w) * 4];
+                    e[0] = bits_of[rm * W + w] | (um & 0xfffu) << 20;
+                    e[1] = bits_of[r * W + w] | (up & 0xfffu) << 20;
+                    e[2] = bits_of[rp * W + w] | ((um >> 12) & 63u) << 20 | ((up >> 12) & 63u) << 26;
+                    e[3] = (uint32_t)b0;
+                }
+            }
+    });
+    out->fits = fits;
 }
 
 void boundary_image(const uint8_t* g, int nx, int ny, int nz, int pad, bool mirror_y, bool mirror_z,

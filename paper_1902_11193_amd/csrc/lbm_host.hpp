@@ -49,7 +49,8 @@ CoordBits coord_bits(int nx, int ny, int nz);
 // moments before (by another XCD, possibly, from the MALL).  So the tiles are
 // as tall as the 32-bit gather offsets allow: node_tile_z takes the tallest
 // height of kNodeTileHeights whose gather span fits with 4-byte elements
-// (else with 2-byte ones).  (512^3 rock, FP32 storage: 0.767 ms per step with
+// (else with 2-byte ones) and with (h + 1) nx + 1 < 2^17 (the bitmap index's
+// base differences, below).  (512^3 rock, FP32 storage: 0.767 ms per step with
 // 16-plane tiles, 0.745 with 64, 0.738 with 96 or 128; the 16-bit storages
 // within 0.5%.)  The choice depends on the image alone, so every storage and
 // every call that orders the nodes agrees on it.
@@ -100,27 +101,37 @@ void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_
 // nx - 1 and position nx + 1 repeats voxel 0 (the periodic wrap).  Word w of a
 // row covers positions kWordStep w .. kWordStep w + 19: consecutive words
 // overlap by two positions, so the window x .. x + 2 (voxels x - 1, x, x + 1)
-// of voxel x lies inside word x / kWordStep.  A word's 8-byte record holds its
-// 20 bits with the row's fluid count above them, and the node number counting
-// real voxels before the word (minus the left pad bit on word 0).  For every row
-// (y, z) and word w the array holds the records of rows y - 1, y, y + 1
-// (periodic in y) of plane z side by side, 24 bytes, stored by (z, y, w): a
-// node reads its nine rows with one 16-byte and one 8-byte load per plane,
-// and the nodes of a row read consecutive bytes.  Each node also keeps its
-// packed voxel coordinate.
+// of voxel x lies inside word x / kWordStep.  The base of a row word is the
+// node number counting the row's real voxels before it (minus the left pad
+// bit on word 0).  For every row (y, z) and word w one 16-byte entry holds the
+// 20 bits of word w of rows y - 1, y, y + 1 (periodic in y) of plane z, the
+// base of the word in row y, and the bases in rows y - 1 and y + 1 as 18-bit
+// differences dm, dp from it:
+//   e[0] = bits(y - 1) | (dm & 0xfff) << 20
+//   e[1] = bits(y)     | (dp & 0xfff) << 20
+//   e[2] = bits(y + 1) | ((dm >> 12) & 63) << 20 | ((dp >> 12) & 63) << 26
+//   e[3] = base(y)
+// so a node reads its nine rows with three 16-byte loads, entries (z - 1, y,
+// w), (z, y, w), (z + 1, y, w), and the nodes of a row read consecutive
+// entries.  Two things stay outside the entries and are read only by the
+// nodes that need them: the bases of every row word (`base`), for row y - 1
+// of y = 0 and row y + 1 of y = ny - 1 across the periodic y wrap, a tile
+// apart in the node order; and each row's fluid count (`count`), which the x
+// wrap needs at x = 0 and x = nx - 1.  Every other difference is at most
+// (h + 1) nx + 1 for z-tiles of h planes, below 2^17 with node_tile_z's
+// height.  Each node also keeps its packed voxel coordinate.
 constexpr int kWordStep = 18;
-struct RowRec {
-    uint32_t lo;  // bits 0..19: the word's positions; bits 20..31: the row's fluid count
-    int32_t base;
-};
-static_assert(sizeof(RowRec) == 8, "RowRec is one 8-byte record");
+constexpr int kDeltaBits = 18;
 inline int words_per_row(int nx) { return (nx - 1) / kWordStep + 1; }
-constexpr int kBitmapMaxNx = 4095;  // the row count has 12 bits
+constexpr int kBitmapMaxNx = 4095;
 struct BitmapIndex {
-    int words = 0;  // records per row
+    int words = 0;  // words per row
     CoordBits bits{};
+    bool fits = true;              // every used difference fits kDeltaBits
     std::vector<uint32_t> coords;  // [nf]
-    std::vector<RowRec> rec;       // [nz][ny][words][3]: rows y - 1, y, y + 1
+    std::vector<uint32_t> ent;     // [nz][ny][words][4]
+    std::vector<int32_t> base;     // [nz][ny][words]
+    std::vector<uint32_t> count;   // [nz][ny]
 };
 // mirror_y: symmetry planes on the y faces (Sec. 2.3): row y - 1 of row 0 and
 // row y + 1 of row ny - 1 are those rows themselves (their ghost images)

@@ -284,12 +284,17 @@ struct TableIdx {
     }
 };
 
-// Row-word records of the padded bit strings built on the host: word w of a
-// row covers padded positions 18 w .. 18 w + 19 (position x + 1 is voxel x,
-// the two ends repeat the opposite voxel: periodic x), so the window of voxel
-// x lies in word x / 18.  A record is 8 bytes {20 bits | row count << 20,
-// base}; entry (z, y, w) holds the records of rows y - 1, y, y + 1 of plane
-// z, 24 bytes: one 16-byte and one 8-byte load.
+// Row words of the padded bit strings built on the host: word w of a row
+// covers padded positions 18 w .. 18 w + 19 (position x + 1 is voxel x, the
+// two ends repeat the opposite voxel: periodic x), so the window of voxel x
+// lies in word x / 18.  Entry (z, y, w), 16 bytes: the 20 bits of word w of
+// rows y - 1, y, y + 1 of plane z, the node base of the word in row y and, as
+// 18-bit differences from it split over the bits' spare high bits, the bases
+// in rows y - 1 and y + 1.  A node reads the entries of planes z - 1, z,
+// z + 1: three 16-byte loads.  Across the periodic y wrap (row y - 1 of
+// y = 0, row y + 1 of y = ny - 1) the base comes from the per-word base
+// array instead, and the x wrap (x = 0 or nx - 1) takes the rows' fluid
+// counts from the per-row count array; only nodes there read them.
 constexpr uint32_t kWordStep = 18;
 // (a & mask) | (b & ~mask) in one instruction
 __device__ __forceinline__ uint32_t bit_select(uint32_t mask, uint32_t a, uint32_t b) {
@@ -299,7 +304,9 @@ __device__ __forceinline__ uint32_t bit_select(uint32_t mask, uint32_t a, uint32
 }
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
-    const uint2* __restrict__ rec;
+    const uint4* __restrict__ ent;
+    const int32_t* __restrict__ bases;
+    const uint32_t* __restrict__ counts;
     uint32_t nx, ny, nz, R, bx, by;  // R: words per row
     // entry offsets from plane z to the plane read as z - 1 at z = 0 and as
     // z + 1 at z = nz - 1: the periodic wrap, or 0 (the plane itself, its
@@ -312,16 +319,17 @@ struct BitmapIdx {
         int32_t rm, r0, rp;
         uint32_t bits;
     };
-    __device__ __forceinline__ Row3 decode(uint2 rec8, uint32_t x, bool x_first, bool x_last) const {
-        const uint32_t lo = rec8.x;
+    // lo: the word's 20 bits (higher bits ignored); base: node number before
+    // the word; count: the row's fluid voxels (read at x = 0 and nx - 1 only)
+    __device__ __forceinline__ Row3 decode(uint32_t lo, int32_t base, uint32_t count, uint32_t x, bool x_first,
+                                           bool x_last) const {
         const uint32_t sh = x - (x / kWordStep) * kWordStep;
-        const int32_t count = (int32_t)(lo >> 20);
         Row3 r;
         r.bits = __builtin_amdgcn_ubfe(lo, sh, 3u);   // padded positions x..x+2
         const int32_t below = (int32_t)__popc(__builtin_amdgcn_ubfe(lo, 0u, sh));
-        r.r0 = (int32_t)rec8.y + below + (int32_t)(r.bits & 1u);
-        r.rm = r.r0 - 1 + (x_first ? count : 0);
-        r.rp = r.r0 + (int32_t)((r.bits >> 1) & 1u) - (x_last ? count : 0);
+        r.r0 = base + below + (int32_t)(r.bits & 1u);
+        r.rm = r.r0 - 1 + (x_first ? (int32_t)count : 0);
+        r.rp = r.r0 + (int32_t)((r.bits >> 1) & 1u) - (x_last ? (int32_t)count : 0);
         return r;
     }
     using Pre = uint32_t;  // the node's packed coordinate, loaded ahead of use
@@ -331,28 +339,23 @@ struct BitmapIdx {
         const uint32_t x = c & ((1u << bx) - 1u);
         return x == 0 ? 1u : (x == nx - 1 ? 2u : 0u);
     }
-    // per plane z - 1, z, z + 1: rows y - 1 and y (a), row y + 1 (b)
+    // rows y - 1 of y = 0 and y + 1 of y = ny - 1 lie across the periodic y wrap
+    __device__ __forceinline__ bool y_wraps() const { return ny > 1u && !(sym & 1u); }
     struct Raw {
-        uint4 a[3];
-        uint2 b[3];
-        // the nine rows around the node: (y, z) and its y / z neighbours
-        __device__ __forceinline__ uint2 own() const { return make_uint2(a[1].z, a[1].w); }
-        __device__ __forceinline__ uint2 ym() const { return make_uint2(a[1].x, a[1].y); }
-        __device__ __forceinline__ uint2 yp() const { return b[1]; }
-        __device__ __forceinline__ uint2 zm() const { return make_uint2(a[0].z, a[0].w); }
-        __device__ __forceinline__ uint2 zp() const { return make_uint2(a[2].z, a[2].w); }
-        __device__ __forceinline__ uint2 mm() const { return make_uint2(a[0].x, a[0].y); }  // y - 1, z - 1
-        __device__ __forceinline__ uint2 pm() const { return b[0]; }                        // y + 1, z - 1
-        __device__ __forceinline__ uint2 mp() const { return make_uint2(a[2].x, a[2].y); }  // y - 1, z + 1
-        __device__ __forceinline__ uint2 pp() const { return b[2]; }                        // y + 1, z + 1
+        uint4 a[3];       // entries of planes z - 1, z, z + 1
+        uint32_t cnt[5];  // x = 0 or nx - 1: counts of rows (y, z), (y - 1, z), (y + 1, z), (y, z - 1), (y, z + 1)
+        int32_t fb[3];    // across the y wrap: base of the wrapped row's word in planes z - 1, z, z + 1
     };
-    // two records (16 bytes) at an 8-byte aligned address
-    static __device__ __forceinline__ uint4 load16(const uint2* p) {
-        typedef uint32_t V4 __attribute__((ext_vector_type(4), aligned(8)));
-        const V4 v = *reinterpret_cast<const V4*>(p);
-        return make_uint4(v.x, v.y, v.z, v.w);
+    // the 18-bit base differences of rows y - 1 (dm) and y + 1 (dp)
+    static __device__ __forceinline__ int32_t sext18(uint32_t v) { return (int32_t)(v << 14) >> 14; }
+    static __device__ __forceinline__ int32_t dm(const uint4& e) {
+        return sext18((e.x >> 20) | ((e.z >> 20) & 63u) << 12);
     }
-    // issue the six record loads of the node with packed coordinate c
+    static __device__ __forceinline__ int32_t dp(const uint4& e) {
+        return sext18((e.y >> 20) | ((e.z >> 26) & 63u) << 12);
+    }
+    // issue the entry loads of the node with packed coordinate c (and, at the
+    // x or y wrap, its count or base loads)
     __device__ __forceinline__ void load(uint32_t, Pre c, Raw& r) const {
         const uint32_t x = c & ((1u << bx) - 1u);
         const uint32_t y = (c >> bx) & ((1u << by) - 1u);
@@ -361,16 +364,30 @@ struct BitmapIdx {
         const uint32_t e = (z * ny + y) * R + x / kWordStep;    // entry (z, y, w)
         const uint32_t em = e + (z == 0 ? zlo : 0u - plane);
         const uint32_t ep = e + (z == nz - 1 ? zhi : plane);
-        const uint2* pm = rec + (uint64_t)em * 3u;
-        const uint2* p0 = rec + (uint64_t)e * 3u;
-        const uint2* pp = rec + (uint64_t)ep * 3u;
         __builtin_amdgcn_sched_barrier(0);
-        r.a[0] = load16(pm);
-        r.b[0] = pm[2];
-        r.a[1] = load16(p0);
-        r.b[1] = p0[2];
-        r.a[2] = load16(pp);
-        r.b[2] = pp[2];
+        r.a[0] = ent[em];
+        r.a[1] = ent[e];
+        r.a[2] = ent[ep];
+        unroll<5>([&](auto k) { r.cnt[decltype(k)::value] = 0u; });
+        unroll<3>([&](auto k) { r.fb[decltype(k)::value] = 0; });
+        if (x == 0u || x == nx - 1u) {
+            const uint32_t ym = y == 0u ? ((sym & 1u) ? 0u : ny - 1u) : y - 1u;
+            const uint32_t yp = y == ny - 1u ? ((sym & 1u) ? y : 0u) : y + 1u;
+            const uint32_t zm = z == 0u ? ((sym & 2u) ? 0u : nz - 1u) : z - 1u;
+            const uint32_t zp = z == nz - 1u ? ((sym & 2u) ? z : 0u) : z + 1u;
+            r.cnt[0] = counts[z * ny + y];
+            r.cnt[1] = counts[z * ny + ym];
+            r.cnt[2] = counts[z * ny + yp];
+            r.cnt[3] = counts[zm * ny + y];
+            r.cnt[4] = counts[zp * ny + y];
+        }
+        if (y_wraps() && (y == 0u || y == ny - 1u)) {
+            // the wrapped row: ny - 1 for y = 0, 0 for y = ny - 1
+            const uint32_t d = y == 0u ? (ny - 1u) * R : 0u - (ny - 1u) * R;
+            r.fb[0] = bases[em + d];
+            r.fb[1] = bases[e + d];
+            r.fb[2] = bases[ep + d];
+        }
     }
     // Calls put(I, row, which) for the 18 directions I of node c: the source
     // voxel x - c_I is voxel x + which (which = -1, 0, +1) of the decoded
@@ -390,31 +407,37 @@ struct BitmapIdx {
     __device__ __forceinline__ void visit(const Raw& r, Pre c, Put&& put) const {
         using std::integral_constant;
         const uint32_t x = c & ((1u << bx) - 1u);
+        const uint32_t y = (c >> bx) & ((1u << by) - 1u);
         const bool xf = x == 0, xl = x == nx - 1;
+        const bool wm = y_wraps() && y == 0u, wp = y_wraps() && y == ny - 1u;
+        // bases of rows y - 1 and y + 1 in the entry of plane k
+        auto bm = [&](int k) { return wm ? r.fb[k] : (int32_t)r.a[k].w + dm(r.a[k]); };
+        auto bp = [&](int k) { return wp ? r.fb[k] : (int32_t)r.a[k].w + dp(r.a[k]); };
         // source x' = x - c_x: c_x = +1 reads x - 1 (which -1), c_x = -1 reads x + 1
-        const Row3 o = decode(r.own(), x, xf, xl);
+        const Row3 o = decode(r.a[1].y, (int32_t)r.a[1].w, r.cnt[0], x, xf, xl);
         put(integral_constant<int, 1>{}, o, -1);
         put(integral_constant<int, 2>{}, o, +1);
-        const Row3 a = decode(r.ym(), x, xf, xl);   // c_y = +1
+        const Row3 a = decode(r.a[1].x, bm(1), r.cnt[1], x, xf, xl);   // c_y = +1
         put(integral_constant<int, 3>{}, a, 0);
         put(integral_constant<int, 7>{}, a, -1);
         put(integral_constant<int, 10>{}, a, +1);
-        const Row3 b = decode(r.yp(), x, xf, xl);   // c_y = -1
+        const Row3 b = decode(r.a[1].z, bp(1), r.cnt[2], x, xf, xl);   // c_y = -1
         put(integral_constant<int, 4>{}, b, 0);
         put(integral_constant<int, 8>{}, b, +1);
         put(integral_constant<int, 9>{}, b, -1);
-        const Row3 d = decode(r.zm(), x, xf, xl);   // c_z = +1
+        const Row3 d = decode(r.a[0].y, (int32_t)r.a[0].w, r.cnt[3], x, xf, xl);   // c_z = +1
         put(integral_constant<int, 5>{}, d, 0);
         put(integral_constant<int, 11>{}, d, -1);
         put(integral_constant<int, 14>{}, d, +1);
-        const Row3 e = decode(r.zp(), x, xf, xl);   // c_z = -1
+        const Row3 e = decode(r.a[2].y, (int32_t)r.a[2].w, r.cnt[4], x, xf, xl);   // c_z = -1
         put(integral_constant<int, 6>{}, e, 0);
         put(integral_constant<int, 12>{}, e, +1);
         put(integral_constant<int, 13>{}, e, -1);
-        put(integral_constant<int, 15>{}, decode(r.mm(), x, xf, xl), 0);
-        put(integral_constant<int, 16>{}, decode(r.pp(), x, xf, xl), 0);
-        put(integral_constant<int, 17>{}, decode(r.mp(), x, xf, xl), 0);
-        put(integral_constant<int, 18>{}, decode(r.pm(), x, xf, xl), 0);
+        // the corner rows only give voxel x, which needs no count
+        put(integral_constant<int, 15>{}, decode(r.a[0].x, bm(0), 0u, x, false, false), 0);   // y - 1, z - 1
+        put(integral_constant<int, 16>{}, decode(r.a[2].z, bp(2), 0u, x, false, false), 0);   // y + 1, z + 1
+        put(integral_constant<int, 17>{}, decode(r.a[2].x, bm(2), 0u, x, false, false), 0);   // y - 1, z + 1
+        put(integral_constant<int, 18>{}, decode(r.a[0].z, bp(0), 0u, x, false, false), 0);   // y + 1, z - 1
     }
     // node number of voxel x + which of a decoded row, and all ones when it is fluid
     static __device__ __forceinline__ uint32_t src_node(const Row3& w, int which) {
@@ -430,7 +453,7 @@ struct BitmapIdx {
     //
     // SYM: symmetry planes on the y and/or z faces (Sec. 2.3).  A pull that
     // would leave the box through such a face reads the ghost row or plane,
-    // the boundary layer itself (the records and zlo / zhi), and takes the
+    // the boundary layer itself (the entries and zlo / zhi), and takes the
     // population whose velocity is mirrored in that axis: the mirror image
     // of the flow on the other side of the plane sends it back.
     template <class T, int S, bool WB, bool SYM = false>
@@ -1116,7 +1139,7 @@ __device__ __forceinline__ Vec3 gquad(float vx, float vy, float vz, const Mom& w
 // so an FP32 sum runs over at most one segment.  Each accumulator value is
 // touched once per step, so it is read and written with non-temporal
 // accesses that leave L2 to the gathered lines.  Software pipeline as in
-// k_step: the index records of the next node are loaded and decoded while
+// k_step: the index entries of the next node are loaded and decoded while
 // this node's 38 gathers are in flight.  It is launched with one block per
 // compute unit (its two gathered arrays make it bound by L2 misses, not by
 // latency), where the registers this pipeline needs (151) cost no occupancy.
@@ -1323,7 +1346,7 @@ BitmapIdx bitmap_view(const IndexView& v) {
     const uint32_t plane = (uint32_t)v.ny * (uint32_t)v.R;         // entries per plane
     const uint32_t wrap = (uint32_t)(v.nz - 1) * plane;
     const bool mz = (v.sym & 2) != 0;
-    return BitmapIdx{v.coords, static_cast<const uint2*>(v.rec), (uint32_t)v.nx, (uint32_t)v.ny,
+    return BitmapIdx{v.coords, static_cast<const uint4*>(v.ent), v.base, v.count, (uint32_t)v.nx, (uint32_t)v.ny,
                      (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by,
                      mz ? 0u : wrap, mz ? 0u : 0u - wrap, (uint32_t)v.sym};
 }

@@ -38,10 +38,12 @@ struct IndexView {
     int64_t slack;              // elements between a chunk's gather base and the chunk (gather_span)
     const int32_t* table;       // kTable: [18][stride] pull sources, -1 = solid
     const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
-    const void* rec;            // kBitmap: [nz][ny][R][3] 8-byte records (rows y - 1, y, y + 1)
+    const void* ent;            // kBitmap: [nz][ny][R] 16-byte entries (rows y - 1, y, y + 1)
+    const int32_t* base;        // kBitmap: [nz][ny][R] node base of every row word
+    const uint32_t* count;      // kBitmap: [nz][ny] fluid voxels per row
     int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = words per row
     int sym;                    // kBitmap: symmetry planes, bit 0 on the y faces, bit 1 on the z faces
-                                // (the records then hold the y ghost rows)
+                                // (the entries then hold the y ghost rows)
 };
 
 struct StepLaunch {

@@ -1,20 +1,21 @@
 // Brute-force check of the bitmap neighbour index on random periodic images:
 // for every fluid node, the pull sources decoded from its packed coordinate
-// and the records of its nine rows must equal the sources of the plain
+// and the entries of its three planes must equal the sources of the plain
 // neighbour table -- the node at x - c_i, or -1 where that voxel is solid --
-// and every record load must lie inside the record array.  The decode below
-// is a CPU model of the step kernel's: entry (z, y, w) holds the 8-byte
-// records of word w of rows y - 1, y, y + 1 of plane z; a node reads the
-// entries (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 18; the window
-// of voxels x - 1, x, x + 1 is three bits of a record starting at position
-// x mod 18, node numbers follow from a population count, and the x wrap uses
-// the row's fluid count.  With symmetry planes on the y and/or z faces
-// (build_bitmap's mirror_y; the kernel reads plane z itself for z - 1 at
-// z = 0 and for z + 1 at z = nz - 1 when the z faces are mirrors) the source
-// of a pull that leaves the box through such a face is the voxel reached by
-// the step's other components, the image's own boundary layer; every node's
-// decoded sources are compared with that rule written out here.  Exit status
-// 0 when every case holds.
+// and every load must lie inside its array.  The decode below is a CPU model
+// of the step kernel's: entry (z, y, w) holds word w's 20 bits of rows y - 1,
+// y, y + 1 of plane z, the base of the word in row y and the 18-bit
+// differences to the bases in rows y - 1 and y + 1; a node reads the entries
+// (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 18, the per-word base
+// of the wrapped row across the periodic y wrap, and the rows' fluid counts
+// at the x wrap; the window of voxels x - 1, x, x + 1 is three bits starting
+// at position x mod 18 and node numbers follow from a population count.  With
+// symmetry planes on the y and/or z faces (build_bitmap's mirror_y; the kernel
+// reads plane z itself for z - 1 at z = 0 and for z + 1 at z = nz - 1 when the
+// z faces are mirrors) the source of a pull that leaves the box through such a
+// face is the voxel reached by the step's other components, the image's own
+// boundary layer; every node's decoded sources are compared with that rule
+// written out here.  Exit status 0 when every case holds.
 #include "lbm_host.hpp"
 #include <cstdio>
 #include <random>
@@ -26,17 +27,17 @@ struct Row3 {
     int64_t rm, r0, rp;
     uint32_t bits;
 };
-Row3 decode(const RowRec& w, int x, int nx) {
+Row3 decode(uint32_t lo, int64_t base, int64_t count, int x, int nx) {
     const uint32_t sh = (uint32_t)(x % kWordStep);
-    const int64_t count = (int64_t)(w.lo >> 20);
     Row3 r;
-    r.bits = (w.lo >> sh) & 7u;
-    const uint32_t below = (uint32_t)__builtin_popcount(w.lo & ((1u << sh) - 1u));
-    r.r0 = (int64_t)w.base + below + (r.bits & 1u);
+    r.bits = (lo >> sh) & 7u;
+    const uint32_t below = (uint32_t)__builtin_popcount(lo & ((1u << sh) - 1u));
+    r.r0 = base + below + (r.bits & 1u);
     r.rm = r.r0 - 1 + (x == 0 ? count : 0);
     r.rp = r.r0 + ((r.bits >> 1) & 1u) - (x == nx - 1 ? count : 0);
     return r;
 }
+int64_t sext18(uint32_t v) { return (int64_t)((int32_t)(v << 14) >> 14); }
 // source node of the voxel at offset dx (-1, 0, +1) in the decoded row, or -1
 int64_t pick(const Row3& w, int dx) {
     if (!((w.bits >> (dx + 1)) & 1u)) return -1;
@@ -52,7 +53,7 @@ int main() {
         int nx = it < 17 ? edge_nx[it] : 1 + (int)(rng() % 100);
         int ny = 1 + (int)(rng() % 9), nz = 1 + (int)(rng() % 40);
         double phi = (rng() % 100) / 100.0;
-        if (it == 17 || it == 18) {  // the longest rows the 12-bit count holds, nearly or fully fluid
+        if (it == 17 || it == 18) {  // the longest rows the bitmap index holds, nearly or fully fluid
             nx = kBitmapMaxNx;
             ny = 2;
             nz = 3;
@@ -81,30 +82,68 @@ int main() {
         BitmapIndex bm;
         build_bitmap(g.data(), nx, ny, nz, nf, &bm, my);
         const int W = bm.words;
-        const int64_t bytes = (int64_t)bm.rec.size() * 8;
-        if (W != words_per_row(nx) || (int64_t)bm.rec.size() != (int64_t)nz * ny * W * 3) { ++bad; continue; }
+        const int64_t nent = (int64_t)nz * ny * W;
+        if (W != words_per_row(nx) || !bm.fits || (int64_t)bm.ent.size() != nent * 4 ||
+            (int64_t)bm.base.size() != nent || (int64_t)bm.count.size() != (int64_t)nz * ny) { ++bad; continue; }
+        auto in = [&](int64_t i, int64_t size, const char* what, int64_t n) {
+            if (i >= 0 && i < size) return true;
+            if (bad < 10) printf("OUT %s dims %d %d %d node %lld index %lld size %lld\n", what, nx, ny, nz,
+                                 (long long)n, (long long)i, (long long)size);
+            ++bad;
+            return false;
+        };
         for (int64_t n = 0; n < nf; ++n) {
             const uint32_t c = bm.coords[n];
             const int x = (int)(c & ((1u << cb.bx) - 1u));
             const int y = (int)((c >> cb.bx) & ((1u << cb.by) - 1u));
             const int z = (int)((uint64_t)c >> (cb.bx + cb.by));
-            // the kernel's byte offsets: entry (zz, y, w), 16 then 8 bytes
-            RowRec rows[3][3];  // [plane z-1, z, z+1][row y-1, y, y+1]
-            for (int dz = -1; dz <= 1; ++dz) {
+            const int w = x / kWordStep;
+            // the kernel's loads: three entries, the wrapped rows' bases, the counts
+            int64_t ek[3];
+            uint32_t E[3][4];
+            bool ok = true;
+            for (int k = 0; k < 3; ++k) {
+                const int dz = k - 1;
                 int zz = (z + dz + nz) % nz;
                 if (mz && (z + dz < 0 || z + dz >= nz)) zz = z;   // ghost plane: the boundary plane itself
-                const int64_t o = (((int64_t)zz * ny + y) * W + x / kWordStep) * 24;
-                if (o < 0 || o + 24 > bytes || o % 8 != 0) {
-                    if (bad < 10) printf("OUT dims %d %d %d node %lld offset %lld bytes %lld\n", nx, ny, nz,
-                                         (long long)n, (long long)o, (long long)bytes);
-                    ++bad;
-                    continue;
+                ek[k] = ((int64_t)zz * ny + y) * W + w;
+                ok = ok && in(ek[k], nent, "entry", n);
+                if (ok)
+                    for (int q = 0; q < 4; ++q) E[k][q] = bm.ent[(size_t)ek[k] * 4 + q];
+            }
+            if (!ok) continue;
+            const bool ywrap = ny > 1 && !my;
+            const bool wm = ywrap && y == 0, wp = ywrap && y == ny - 1;
+            int64_t fb[3] = {0, 0, 0};
+            if (wm || wp)
+                for (int k = 0; k < 3; ++k) {
+                    const int64_t i = ek[k] + (wm ? (int64_t)(ny - 1) * W : -(int64_t)(ny - 1) * W);
+                    if (in(i, nent, "base", n)) fb[k] = bm.base[i];
                 }
-                for (int k = 0; k < 3; ++k) rows[dz + 1][k] = bm.rec[o / 8 + k];
+            int64_t cnt[5] = {0, 0, 0, 0, 0};
+            if (x == 0 || x == nx - 1) {
+                const int ym = y == 0 ? (my ? 0 : ny - 1) : y - 1, yp = y == ny - 1 ? (my ? y : 0) : y + 1;
+                const int zm = z == 0 ? (mz ? 0 : nz - 1) : z - 1, zp = z == nz - 1 ? (mz ? z : 0) : z + 1;
+                const int64_t rows[5] = {(int64_t)z * ny + y, (int64_t)z * ny + ym, (int64_t)z * ny + yp,
+                                         (int64_t)zm * ny + y, (int64_t)zp * ny + y};
+                for (int k = 0; k < 5; ++k)
+                    if (in(rows[k], (int64_t)nz * ny, "count", n)) cnt[k] = bm.count[rows[k]];
+            }
+            // rows[plane z-1, z, z+1][row y-1, y, y+1]
+            Row3 rows[3][3];
+            for (int k = 0; k < 3; ++k) {
+                const int64_t b0 = (int32_t)E[k][3];
+                const int64_t dm = sext18((E[k][0] >> 20) | ((E[k][2] >> 20) & 63u) << 12);
+                const int64_t dp = sext18((E[k][1] >> 20) | ((E[k][2] >> 26) & 63u) << 12);
+                const int64_t cm = k == 1 ? cnt[1] : 0, c0 = k == 1 ? cnt[0] : (k == 0 ? cnt[3] : cnt[4]),
+                              cp = k == 1 ? cnt[2] : 0;
+                rows[k][0] = decode(E[k][0] & 0xfffffu, wm ? fb[k] : b0 + dm, cm, x, nx);
+                rows[k][1] = decode(E[k][1] & 0xfffffu, b0, c0, x, nx);
+                rows[k][2] = decode(E[k][2] & 0xfffffu, wp ? fb[k] : b0 + dp, cp, x, nx);
             }
             for (int i = 1; i < 19; ++i) {
                 // the source voxel is x - c_i
-                const Row3 r = decode(rows[1 - kC[i][2]][1 - kC[i][1]], x, nx);
+                const Row3& r = rows[1 - kC[i][2]][1 - kC[i][1]];
                 const int64_t got = pick(r, -kC[i][0]);
                 int64_t want = t[(size_t)(i - 1) * np + n];
                 if (my || mz) {
