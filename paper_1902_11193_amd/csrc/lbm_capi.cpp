@@ -56,7 +56,7 @@ size_t state_bytes(int storage, int64_t np) {
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
-    size_t A, B, table, coords, ent, base, count, partials, ring, total;
+    size_t A, B, table, coords, ent, wrap, count, partials, ring, total;
 };
 
 Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int ny, int nz) {
@@ -76,10 +76,10 @@ Layout layout(int64_t np, int64_t nf, int storage, int index_kind, int nx, int n
         off += align256((size_t)std::max<int64_t>(nf, 1) * 4);
         L.ent = off;
         off += align256(words * 16);
-        L.base = off;
-        off += align256(words * 4);
+        L.wrap = off;
+        off += align256((size_t)nz * 2 * lbm::words_per_row(nx) * 16);
         L.count = off;
-        off += align256((size_t)ny * nz * 4);
+        off += align256((size_t)ny * nz * 16);
     }
     // the reduction scratch, kReductionBytes at the end (lbm_setup_static
     // contexts keep it in the static array instead)
@@ -589,8 +589,8 @@ int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, d
             return cleanup(fail(LBM_ERANGE, "the bitmap index's row-base differences exceed 18 bits"));
         v.coords = reinterpret_cast<const uint32_t*>(c->ws + c->L.coords);
         v.ent = c->ws + c->L.ent;
-        v.base = reinterpret_cast<const int32_t*>(c->ws + c->L.base);
-        v.count = reinterpret_cast<const uint32_t*>(c->ws + c->L.count);
+        v.wrap = c->ws + c->L.wrap;
+        v.count = c->ws + c->L.count;
         v.nx = nx;
         v.ny = ny;
         v.nz = nz;
@@ -603,7 +603,7 @@ int setup_impl(lbm_ctx** ctx, const uint8_t* geometry, int nx, int ny, int nz, d
             he = hipMemcpyAsync(c->ws + c->L.ent, bm.ent.data(), bm.ent.size() * 4, hipMemcpyHostToDevice,
                                 c->stream);
         if (he == hipSuccess)
-            he = hipMemcpyAsync(c->ws + c->L.base, bm.base.data(), bm.base.size() * 4, hipMemcpyHostToDevice,
+            he = hipMemcpyAsync(c->ws + c->L.wrap, bm.wrap.data(), bm.wrap.size() * 4, hipMemcpyHostToDevice,
                                 c->stream);
         if (he == hipSuccess)
             he = hipMemcpyAsync(c->ws + c->L.count, bm.count.data(), bm.count.size() * 4, hipMemcpyHostToDevice,
@@ -953,12 +953,17 @@ int lbm_set_symmetry(lbm_ctx* c, int mirror_y, int mirror_z) {
     if (sym && c->storage != LBM_F32) return fail(LBM_EINVAL, "symmetry planes need FP32 storage");
     if (sym && c->pressure) return fail(LBM_EINVAL, "symmetry planes cannot be combined with pressure faces");
     if (sym == c->idx.sym) return LBM_OK;
-    // the entries hold ghost rows beyond mirrored y faces (the z ghost planes
-    // are chosen in the kernel); the bases and counts do not change
+    // the entries hold ghost rows beyond mirrored y faces, the counts and wrap
+    // bases the ghost rows and planes (the kernel picks the entries' z ghost
+    // planes itself)
     lbm::BitmapIndex bm;
-    lbm::build_bitmap(c->geom.data(), c->nx, c->ny, c->nz, c->nf, &bm, (sym & 1) != 0);
+    lbm::build_bitmap(c->geom.data(), c->nx, c->ny, c->nz, c->nf, &bm, (sym & 1) != 0, (sym & 2) != 0);
     if (!bm.fits) return fail(LBM_ERANGE, "the bitmap index's row-base differences exceed 18 bits");
     HIP_TRY(hipMemcpyAsync(c->ws + c->L.ent, bm.ent.data(), bm.ent.size() * 4, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.wrap, bm.wrap.data(), bm.wrap.size() * 4, hipMemcpyHostToDevice,
+                           c->stream));
+    HIP_TRY(hipMemcpyAsync(c->ws + c->L.count, bm.count.data(), bm.count.size() * 4, hipMemcpyHostToDevice,
                            c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     c->idx.sym = sym;

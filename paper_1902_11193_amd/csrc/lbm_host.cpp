@@ -278,16 +278,18 @@ void build_table(const uint8_t* g, int nx, int ny, int nz, int64_t nf, int64_t s
     (void)nf;
 }
 
-void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out, bool mirror_y) {
+void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIndex* out, bool mirror_y,
+                  bool mirror_z) {
     const int W = words_per_row(nx);
     const int64_t rows = (int64_t)ny * nz;
     out->words = W;
     out->bits = coord_bits(nx, ny, nz);
     out->coords.assign(nf, 0);
     out->ent.assign((size_t)rows * W * 4, 0u);
-    out->base.assign((size_t)rows * W, 0);
-    out->count.assign((size_t)rows, 0u);
-    std::vector<uint32_t> bits_of((size_t)rows * W, 0u);
+    out->wrap.assign((size_t)nz * 2 * W * 4, 0u);
+    out->count.assign((size_t)rows * 4, 0u);
+    std::vector<uint32_t> bits_of((size_t)rows * W, 0u), count_of((size_t)rows, 0u);
+    std::vector<int32_t> base_of((size_t)rows * W, 0);
     auto start = row_starts(g, nx, ny, nz);
     const int bx = out->bits.bx, by = out->bits.by;
     // every row word's bits and base, every row's count, every node's coordinate
@@ -304,7 +306,7 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                 pad[nx + 1] = pad[1];
                 uint32_t count = 0;
                 for (int x = 0; x < nx; ++x) count += pad[x + 1];
-                out->count[r] = count;
+                count_of[r] = count;
                 int64_t before = 0;  // fluid voxels at real positions [1, kWordStep w)
                 for (int w = 0; w < W; ++w) {
                     uint32_t bits = 0;
@@ -313,7 +315,7 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                         if (q < nx + 2 && pad[q]) bits |= 1u << b;
                     }
                     bits_of[r * W + w] = bits;
-                    out->base[r * W + w] = (int32_t)(rowstart + before - (w == 0 ? pad[0] : 0));
+                    base_of[r * W + w] = (int32_t)(rowstart + before - (w == 0 ? pad[0] : 0));
                     for (int b = 0; b < kWordStep; ++b) {
                         const int q = kWordStep * w + b;
                         if (q >= 1 && q <= nx) before += pad[q];
@@ -325,23 +327,30 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                             (uint32_t)x | ((uint32_t)y << bx) | ((uint32_t)z << (bx + by));
             }
     });
-    // the entries: rows y - 1 and y + 1 periodic in y, or, with symmetry
+    // the neighbouring rows: y - 1 and y + 1 periodic in y, or, with symmetry
     // planes on the y faces, row 0 its own row y - 1 and row ny - 1 its own
-    // row y + 1 (their ghost images); across the periodic wrap the kernel
-    // reads the base from `base` and the difference is left 0
+    // row y + 1 (their ghost images); likewise the planes z - 1 and z + 1.
+    // Across the periodic y wrap the kernel reads the bases from `wrap` and
+    // the entry's difference is left 0.
     const int64_t lim = (int64_t)1 << (kDeltaBits - 1);
     std::atomic<bool> fits{true};
     parallel_slabs(nz, rows * W, [&](int z0, int z1) {
-        for (int z = z0; z < z1; ++z)
+        for (int z = z0; z < z1; ++z) {
+            const int zm = z == 0 ? (mirror_z ? 0 : nz - 1) : z - 1;
+            const int zp = z == nz - 1 ? (mirror_z ? nz - 1 : 0) : z + 1;
             for (int y = 0; y < ny; ++y) {
                 const int ym = y == 0 ? (mirror_y ? 0 : ny - 1) : y - 1;
                 const int yp = y == ny - 1 ? (mirror_y ? ny - 1 : 0) : y + 1;
                 const bool wm = ny > 1 && !mirror_y && y == 0, wp = ny > 1 && !mirror_y && y == ny - 1;
                 const int64_t r = (int64_t)z * ny + y, rm = (int64_t)z * ny + ym, rp = (int64_t)z * ny + yp;
+                uint32_t* cn = &out->count[(size_t)r * 4];
+                cn[0] = count_of[r] | count_of[rm] << 16;
+                cn[1] = count_of[rp] | count_of[(int64_t)zm * ny + y] << 16;
+                cn[2] = count_of[(int64_t)zp * ny + y];
                 for (int w = 0; w < W; ++w) {
-                    const int64_t b0 = out->base[r * W + w];
-                    const int64_t dm = wm ? 0 : out->base[rm * W + w] - b0;
-                    const int64_t dp = wp ? 0 : out->base[rp * W + w] - b0;
+                    const int64_t b0 = base_of[r * W + w];
+                    const int64_t dm = wm ? 0 : base_of[rm * W + w] - b0;
+                    const int64_t dp = wp ? 0 : base_of[rp * W + w] - b0;
                     if (dm < -lim || dm >= lim || dp < -lim || dp >= lim) fits = false;
                     const uint32_t um = (uint32_t)dm, up = (uint32_t)dp;
                     uint32_t* e = &out->ent[(size_t)(r * W + w) * 4];
@@ -351,6 +360,17 @@ void build_bitmap(const uint8_t* g, int nx, int ny, int nz, int64_t nf, BitmapIn
                     e[3] = (uint32_t)b0;
                 }
             }
+            // the rows across the y wrap: row ny - 1 for y = 0 (side 0), row 0 for y = ny - 1 (side 1)
+            for (int side = 0; side < 2; ++side) {
+                const int yw = side == 0 ? ny - 1 : 0;
+                for (int w = 0; w < W; ++w) {
+                    uint32_t* v = &out->wrap[(((size_t)z * 2 + side) * W + w) * 4];
+                    v[0] = (uint32_t)base_of[((int64_t)zm * ny + yw) * W + w];
+                    v[1] = (uint32_t)base_of[((int64_t)z * ny + yw) * W + w];
+                    v[2] = (uint32_t)base_of[((int64_t)zp * ny + yw) * W + w];
+                }
+            }
+        }
     });
     out->fits = fits;
 }

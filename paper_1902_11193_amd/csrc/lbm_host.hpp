@@ -113,13 +113,16 @@ void build_table(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, int64_
 //   e[3] = base(y)
 // so a node reads its nine rows with three 16-byte loads, entries (z - 1, y,
 // w), (z, y, w), (z + 1, y, w), and the nodes of a row read consecutive
-// entries.  Two things stay outside the entries and are read only by the
-// nodes that need them: the bases of every row word (`base`), for row y - 1
-// of y = 0 and row y + 1 of y = ny - 1 across the periodic y wrap, a tile
-// apart in the node order; and each row's fluid count (`count`), which the x
-// wrap needs at x = 0 and x = nx - 1.  Every other difference is at most
-// (h + 1) nx + 1 for z-tiles of h planes, below 2^17 with node_tile_z's
-// height.  Each node also keeps its packed voxel coordinate.
+// entries.  Two things stay outside the entries, each one load for the nodes
+// that need it: for the rows y = 0 and y = ny - 1, `wrap` (z, side, w) holds
+// the bases of word w in the row across the periodic y wrap (row ny - 1 for
+// side 0, row 0 for side 1) in planes z - 1, z, z + 1, a tile apart in the
+// node order; and `count` (z, y) holds the fluid counts of rows (y, z),
+// (y - 1, z), (y + 1, z), (y, z - 1), (y, z + 1) as 16-bit fields {c0 | c1 << 16,
+// c2 | c3 << 16, c4, 0}, which the x wrap needs at x = 0 and x = nx - 1.  Every
+// other difference is at most (h + 1) nx + 1 for z-tiles of h planes, below
+// 2^17 with node_tile_z's height.  Each node also keeps its packed voxel
+// coordinate.
 constexpr int kWordStep = 18;
 constexpr int kDeltaBits = 18;
 inline int words_per_row(int nx) { return (nx - 1) / kWordStep + 1; }
@@ -130,14 +133,16 @@ struct BitmapIndex {
     bool fits = true;              // every used difference fits kDeltaBits
     std::vector<uint32_t> coords;  // [nf]
     std::vector<uint32_t> ent;     // [nz][ny][words][4]
-    std::vector<int32_t> base;     // [nz][ny][words]
-    std::vector<uint32_t> count;   // [nz][ny]
+    std::vector<uint32_t> wrap;    // [nz][2][words][4]
+    std::vector<uint32_t> count;   // [nz][ny][4]
 };
 // mirror_y: symmetry planes on the y faces (Sec. 2.3): row y - 1 of row 0 and
 // row y + 1 of row ny - 1 are those rows themselves (their ghost images)
-// instead of the periodic neighbours.
+// instead of the periodic neighbours.  mirror_z: likewise plane z - 1 of
+// plane 0 and plane z + 1 of plane nz - 1 (for the counts and wrap bases; the
+// kernel picks the planes of the entries itself).
 void build_bitmap(const uint8_t* geom, int nx, int ny, int nz, int64_t nf, BitmapIndex* out,
-                  bool mirror_y = false);
+                  bool mirror_y = false, bool mirror_z = false);
 
 // Non-periodic image stacks (Sec. 2.3): `pad` fluid-only layers before and
 // after the image along x, then the image reflected across its y and/or z

@@ -292,9 +292,10 @@ struct TableIdx {
 // 18-bit differences from it split over the bits' spare high bits, the bases
 // in rows y - 1 and y + 1.  A node reads the entries of planes z - 1, z,
 // z + 1: three 16-byte loads.  Across the periodic y wrap (row y - 1 of
-// y = 0, row y + 1 of y = ny - 1) the base comes from the per-word base
-// array instead, and the x wrap (x = 0 or nx - 1) takes the rows' fluid
-// counts from the per-row count array; only nodes there read them.
+// y = 0, row y + 1 of y = ny - 1) the bases come from one 12-byte slot of the
+// wrap array, and the x wrap (x = 0 or nx - 1) takes the fluid counts of the
+// five rows it crosses from one 12-byte slot of the count array; only nodes
+// there read them.
 constexpr uint32_t kWordStep = 18;
 // (a & mask) | (b & ~mask) in one instruction
 __device__ __forceinline__ uint32_t bit_select(uint32_t mask, uint32_t a, uint32_t b) {
@@ -305,8 +306,8 @@ __device__ __forceinline__ uint32_t bit_select(uint32_t mask, uint32_t a, uint32
 struct BitmapIdx {
     const uint32_t* __restrict__ coords;
     const uint4* __restrict__ ent;
-    const int32_t* __restrict__ bases;
-    const uint32_t* __restrict__ counts;
+    const uint4* __restrict__ wraps;   // [nz][2][R]: bases in planes z - 1, z, z + 1 of the row across the y wrap
+    const uint4* __restrict__ counts;  // [nz][ny]: 16-bit counts of rows (y, z), (y - 1, z), (y + 1, z), (y, z -/+ 1)
     uint32_t nx, ny, nz, R, bx, by;  // R: words per row
     // entry offsets from plane z to the plane read as z - 1 at z = 0 and as
     // z + 1 at z = nz - 1: the periodic wrap, or 0 (the plane itself, its
@@ -343,9 +344,17 @@ struct BitmapIdx {
     __device__ __forceinline__ bool y_wraps() const { return ny > 1u && !(sym & 1u); }
     struct Raw {
         uint4 a[3];       // entries of planes z - 1, z, z + 1
-        uint32_t cnt[5];  // x = 0 or nx - 1: counts of rows (y, z), (y - 1, z), (y + 1, z), (y, z - 1), (y, z + 1)
+        uint32_t cn[3];   // x = 0 or nx - 1: the five rows' counts, 16 bits each
         int32_t fb[3];    // across the y wrap: base of the wrapped row's word in planes z - 1, z, z + 1
     };
+    // 12 bytes at a 16-byte slot
+    static __device__ __forceinline__ void load12(const uint4* p, uint32_t v[3]) {
+        typedef uint32_t V3 __attribute__((ext_vector_type(3), aligned(16)));
+        const V3 t = *reinterpret_cast<const V3*>(p);
+        v[0] = t.x;
+        v[1] = t.y;
+        v[2] = t.z;
+    }
     // the 18-bit base differences of rows y - 1 (dm) and y + 1 (dp)
     static __device__ __forceinline__ int32_t sext18(uint32_t v) { return (int32_t)(v << 14) >> 14; }
     static __device__ __forceinline__ int32_t dm(const uint4& e) {
@@ -354,8 +363,12 @@ struct BitmapIdx {
     static __device__ __forceinline__ int32_t dp(const uint4& e) {
         return sext18((e.y >> 20) | ((e.z >> 26) & 63u) << 12);
     }
-    // issue the entry loads of the node with packed coordinate c (and, at the
-    // x or y wrap, its count or base loads)
+    // issue the entry loads of the node with packed coordinate c and, when a
+    // node of the wave lies on the x or y wrap, the whole wave's count and
+    // wrap slots (in bounds for every node; used only where needed).  One
+    // wave-uniform branch: with one wave per SIMD each branch around these
+    // loads cost the small 128^3 pack's adjoint step about 7%, and loading
+    // them unconditionally cost the 512^3 rock's FP16 step 4%.
     __device__ __forceinline__ void load(uint32_t, Pre c, Raw& r) const {
         const uint32_t x = c & ((1u << bx) - 1u);
         const uint32_t y = (c >> bx) & ((1u << by) - 1u);
@@ -368,25 +381,15 @@ struct BitmapIdx {
         r.a[0] = ent[em];
         r.a[1] = ent[e];
         r.a[2] = ent[ep];
-        unroll<5>([&](auto k) { r.cnt[decltype(k)::value] = 0u; });
-        unroll<3>([&](auto k) { r.fb[decltype(k)::value] = 0; });
-        if (x == 0u || x == nx - 1u) {
-            const uint32_t ym = y == 0u ? ((sym & 1u) ? 0u : ny - 1u) : y - 1u;
-            const uint32_t yp = y == ny - 1u ? ((sym & 1u) ? y : 0u) : y + 1u;
-            const uint32_t zm = z == 0u ? ((sym & 2u) ? 0u : nz - 1u) : z - 1u;
-            const uint32_t zp = z == nz - 1u ? ((sym & 2u) ? z : 0u) : z + 1u;
-            r.cnt[0] = counts[z * ny + y];
-            r.cnt[1] = counts[z * ny + ym];
-            r.cnt[2] = counts[z * ny + yp];
-            r.cnt[3] = counts[zm * ny + y];
-            r.cnt[4] = counts[zp * ny + y];
-        }
-        if (y_wraps() && (y == 0u || y == ny - 1u)) {
-            // the wrapped row: ny - 1 for y = 0, 0 for y = ny - 1
-            const uint32_t d = y == 0u ? (ny - 1u) * R : 0u - (ny - 1u) * R;
-            r.fb[0] = bases[em + d];
-            r.fb[1] = bases[e + d];
-            r.fb[2] = bases[ep + d];
+        unroll<3>([&](auto k) {
+            r.cn[decltype(k)::value] = 0u;
+            r.fb[decltype(k)::value] = 0;
+        });
+        if (__builtin_amdgcn_ballot_w64(x == 0u || x == nx - 1u || y == 0u || y == ny - 1u) != 0) {
+            load12(counts + (z * ny + y), r.cn);
+            uint32_t v[3];
+            load12(wraps + ((z * 2u + (y == 0u ? 0u : 1u)) * R + x / kWordStep), v);
+            unroll<3>([&](auto k) { r.fb[decltype(k)::value] = (int32_t)v[decltype(k)::value]; });
         }
     }
     // Calls put(I, row, which) for the 18 directions I of node c: the source
@@ -414,22 +417,22 @@ struct BitmapIdx {
         auto bm = [&](int k) { return wm ? r.fb[k] : (int32_t)r.a[k].w + dm(r.a[k]); };
         auto bp = [&](int k) { return wp ? r.fb[k] : (int32_t)r.a[k].w + dp(r.a[k]); };
         // source x' = x - c_x: c_x = +1 reads x - 1 (which -1), c_x = -1 reads x + 1
-        const Row3 o = decode(r.a[1].y, (int32_t)r.a[1].w, r.cnt[0], x, xf, xl);
+        const Row3 o = decode(r.a[1].y, (int32_t)r.a[1].w, r.cn[0] & 0xffffu, x, xf, xl);
         put(integral_constant<int, 1>{}, o, -1);
         put(integral_constant<int, 2>{}, o, +1);
-        const Row3 a = decode(r.a[1].x, bm(1), r.cnt[1], x, xf, xl);   // c_y = +1
+        const Row3 a = decode(r.a[1].x, bm(1), r.cn[0] >> 16, x, xf, xl);   // c_y = +1
         put(integral_constant<int, 3>{}, a, 0);
         put(integral_constant<int, 7>{}, a, -1);
         put(integral_constant<int, 10>{}, a, +1);
-        const Row3 b = decode(r.a[1].z, bp(1), r.cnt[2], x, xf, xl);   // c_y = -1
+        const Row3 b = decode(r.a[1].z, bp(1), r.cn[1] & 0xffffu, x, xf, xl);   // c_y = -1
         put(integral_constant<int, 4>{}, b, 0);
         put(integral_constant<int, 8>{}, b, +1);
         put(integral_constant<int, 9>{}, b, -1);
-        const Row3 d = decode(r.a[0].y, (int32_t)r.a[0].w, r.cnt[3], x, xf, xl);   // c_z = +1
+        const Row3 d = decode(r.a[0].y, (int32_t)r.a[0].w, r.cn[1] >> 16, x, xf, xl);   // c_z = +1
         put(integral_constant<int, 5>{}, d, 0);
         put(integral_constant<int, 11>{}, d, -1);
         put(integral_constant<int, 14>{}, d, +1);
-        const Row3 e = decode(r.a[2].y, (int32_t)r.a[2].w, r.cnt[4], x, xf, xl);   // c_z = -1
+        const Row3 e = decode(r.a[2].y, (int32_t)r.a[2].w, r.cn[2], x, xf, xl);   // c_z = -1
         put(integral_constant<int, 6>{}, e, 0);
         put(integral_constant<int, 12>{}, e, +1);
         put(integral_constant<int, 13>{}, e, -1);
@@ -1346,7 +1349,8 @@ BitmapIdx bitmap_view(const IndexView& v) {
     const uint32_t plane = (uint32_t)v.ny * (uint32_t)v.R;         // entries per plane
     const uint32_t wrap = (uint32_t)(v.nz - 1) * plane;
     const bool mz = (v.sym & 2) != 0;
-    return BitmapIdx{v.coords, static_cast<const uint4*>(v.ent), v.base, v.count, (uint32_t)v.nx, (uint32_t)v.ny,
+    return BitmapIdx{v.coords, static_cast<const uint4*>(v.ent), static_cast<const uint4*>(v.wrap),
+                     static_cast<const uint4*>(v.count), (uint32_t)v.nx, (uint32_t)v.ny,
                      (uint32_t)v.nz, (uint32_t)v.R, (uint32_t)v.bx, (uint32_t)v.by,
                      mz ? 0u : wrap, mz ? 0u : 0u - wrap, (uint32_t)v.sym};
 }

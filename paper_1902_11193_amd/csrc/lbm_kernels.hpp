@@ -39,8 +39,8 @@ struct IndexView {
     const int32_t* table;       // kTable: [18][stride] pull sources, -1 = solid
     const uint32_t* coords;     // kBitmap: [nf] packed voxel coordinates
     const void* ent;            // kBitmap: [nz][ny][R] 16-byte entries (rows y - 1, y, y + 1)
-    const int32_t* base;        // kBitmap: [nz][ny][R] node base of every row word
-    const uint32_t* count;      // kBitmap: [nz][ny] fluid voxels per row
+    const void* wrap;           // kBitmap: [nz][2][R] 16-byte slots: bases of the rows across the y wrap
+    const void* count;          // kBitmap: [nz][ny] 16-byte slots: the x wrap's row counts
     int nx, ny, nz, R, bx, by;  // kBitmap geometry; R = words per row
     int sym;                    // kBitmap: symmetry planes, bit 0 on the y faces, bit 1 on the z faces
                                 // (the entries then hold the y ghost rows)

@@ -6,12 +6,13 @@
 // of the step kernel's: entry (z, y, w) holds word w's 20 bits of rows y - 1,
 // y, y + 1 of plane z, the base of the word in row y and the 18-bit
 // differences to the bases in rows y - 1 and y + 1; a node reads the entries
-// (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 18, the per-word base
-// of the wrapped row across the periodic y wrap, and the rows' fluid counts
-// at the x wrap; the window of voxels x - 1, x, x + 1 is three bits starting
+// (z - 1, y, w), (z, y, w), (z + 1, y, w) with w = x / 18, across the
+// periodic y wrap the wrapped row's bases from one slot of the wrap array, and
+// at the x wrap the five rows' fluid counts from one slot of the count array;
+// the window of voxels x - 1, x, x + 1 is three bits starting
 // at position x mod 18 and node numbers follow from a population count.  With
-// symmetry planes on the y and/or z faces (build_bitmap's mirror_y; the kernel
-// reads plane z itself for z - 1 at z = 0 and for z + 1 at z = nz - 1 when the
+// symmetry planes on the y and/or z faces (build_bitmap's mirror_y and
+// mirror_z; the kernel reads plane z itself for z - 1 at z = 0 and for z + 1 at z = nz - 1 when the
 // z faces are mirrors) the source of a pull that leaves the box through such a
 // face is the voxel reached by the step's other components, the image's own
 // boundary layer; every node's decoded sources are compared with that rule
@@ -80,11 +81,12 @@ int main() {
         for (int mirror = 0; mirror < 4; ++mirror) {
         const bool my = mirror & 1, mz = mirror & 2;
         BitmapIndex bm;
-        build_bitmap(g.data(), nx, ny, nz, nf, &bm, my);
+        build_bitmap(g.data(), nx, ny, nz, nf, &bm, my, mz);
         const int W = bm.words;
         const int64_t nent = (int64_t)nz * ny * W;
+        const int64_t nwrap = (int64_t)nz * 2 * W, nrow = (int64_t)nz * ny;
         if (W != words_per_row(nx) || !bm.fits || (int64_t)bm.ent.size() != nent * 4 ||
-            (int64_t)bm.base.size() != nent || (int64_t)bm.count.size() != (int64_t)nz * ny) { ++bad; continue; }
+            (int64_t)bm.wrap.size() != nwrap * 4 || (int64_t)bm.count.size() != nrow * 4) { ++bad; continue; }
         auto in = [&](int64_t i, int64_t size, const char* what, int64_t n) {
             if (i >= 0 && i < size) return true;
             if (bad < 10) printf("OUT %s dims %d %d %d node %lld index %lld size %lld\n", what, nx, ny, nz,
@@ -115,19 +117,22 @@ int main() {
             const bool ywrap = ny > 1 && !my;
             const bool wm = ywrap && y == 0, wp = ywrap && y == ny - 1;
             int64_t fb[3] = {0, 0, 0};
-            if (wm || wp)
-                for (int k = 0; k < 3; ++k) {
-                    const int64_t i = ek[k] + (wm ? (int64_t)(ny - 1) * W : -(int64_t)(ny - 1) * W);
-                    if (in(i, nent, "base", n)) fb[k] = bm.base[i];
-                }
+            if (wm || wp) {
+                const int64_t i = ((int64_t)z * 2 + (wm ? 0 : 1)) * W + w;
+                if (in(i, nwrap, "wrap", n))
+                    for (int k = 0; k < 3; ++k) fb[k] = (int32_t)bm.wrap[(size_t)i * 4 + k];
+            }
             int64_t cnt[5] = {0, 0, 0, 0, 0};
             if (x == 0 || x == nx - 1) {
-                const int ym = y == 0 ? (my ? 0 : ny - 1) : y - 1, yp = y == ny - 1 ? (my ? y : 0) : y + 1;
-                const int zm = z == 0 ? (mz ? 0 : nz - 1) : z - 1, zp = z == nz - 1 ? (mz ? z : 0) : z + 1;
-                const int64_t rows[5] = {(int64_t)z * ny + y, (int64_t)z * ny + ym, (int64_t)z * ny + yp,
-                                         (int64_t)zm * ny + y, (int64_t)zp * ny + y};
-                for (int k = 0; k < 5; ++k)
-                    if (in(rows[k], (int64_t)nz * ny, "count", n)) cnt[k] = bm.count[rows[k]];
+                const int64_t i = (int64_t)z * ny + y;
+                if (in(i, nrow, "count", n)) {
+                    const uint32_t* v = &bm.count[(size_t)i * 4];
+                    cnt[0] = v[0] & 0xffffu;
+                    cnt[1] = v[0] >> 16;
+                    cnt[2] = v[1] & 0xffffu;
+                    cnt[3] = v[1] >> 16;
+                    cnt[4] = v[2];
+                }
             }
             // rows[plane z-1, z, z+1][row y-1, y, y+1]
             Row3 rows[3][3];
