@@ -31,15 +31,18 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per fluid-lattice update: 19 populations read + 19 written.
 ALG_BYTES = {"f32": 19 * 4 * 2, "f16": 19 * 2 * 2, "bf16": 19 * 2 * 2, "f16r": 20 * 2 * 2}
 # Index bytes per node the design adds: the int32 [18] table; or, for the bitmap,
-# one packed coordinate per node plus the row records read once per step
-# (8 bytes per 18 voxels of a row, stored three times: 24 * ny * nz * words).
+# one packed coordinate per node plus the 16-byte entries read once per step
+# (one per 18 voxels of a row: 16 * ny * nz * words), the 16-byte count slots
+# (one per row, read at the x wrap) and the 16-byte wrap slots (two per plane
+# and word, read at the y wrap), all counted as read once.
 
 
 def index_bytes(index: str, shape, nf: int) -> float:
     if index == "table":
         return 18 * 4
     nz, ny, nx = shape
-    return 4 + 24 * ny * nz * ((nx + 17) // 18) / nf
+    words = (nx + 17) // 18
+    return 4 + (16 * ny * nz * words + 16 * ny * nz + 32 * nz * words) / nf
 # Adjoint reverse step per node: read lambda^{n+1} and fh^{n-1}, write lambda^n
 # (228 B), and update the node's running FP32 sum of dk/dg(x) (read 12 B,
 # write 12 B; the first step of a checkpoint segment writes it only).

@@ -105,10 +105,10 @@ extern "C" {
  *                   entry (the 20 fluid bits of that word in rows y - 1, y,
  *                   y + 1 of the plane, the node number before the word in
  *                   row y and the differences to those of rows y - 1 and
- *                   y + 1) and that node number again (for the rows across
- *                   the periodic y wrap), and each row's fluid count; the
+ *                   y + 1), small slots for the rows across the periodic y
+ *                   wrap and the fluid counts the periodic x wrap needs; the
  *                   source node of a link is found by a population count.
- *                   4 bytes per node + 1.12 bytes per voxel.  Needs
+ *                   4 bytes per node + about 0.94 bytes per voxel.  Needs
  *                   ceil(log2 nx) + ceil(log2 ny) + ceil(log2 nz) <= 32,
  *                   nx <= 4095 and fewer than 2^32 row words
  *                   (ny nz ceil(nx / 18)). */
