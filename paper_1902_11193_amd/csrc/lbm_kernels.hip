@@ -208,6 +208,7 @@ struct TableIdx {
     struct Raw {
         int32_t t[19];
     };
+    template <bool BRANCH = true>
     __device__ __forceinline__ void load(uint32_t n, Pre, Raw& r) const {
         unroll<18>([&](auto k) {
             constexpr int i = decltype(k)::value + 1;
@@ -363,12 +364,14 @@ struct BitmapIdx {
     static __device__ __forceinline__ int32_t dp(const uint4& e) {
         return sext18((e.y >> 20) | ((e.z >> 26) & 63u) << 12);
     }
-    // issue the entry loads of the node with packed coordinate c and, when a
-    // node of the wave lies on the x or y wrap, the whole wave's count and
-    // wrap slots (in bounds for every node; used only where needed).  One
-    // wave-uniform branch: with one wave per SIMD each branch around these
-    // loads cost the small 128^3 pack's adjoint step about 7%, and loading
-    // them unconditionally cost the 512^3 rock's FP16 step 4%.
+    // issue the entry loads of the node with packed coordinate c and its count
+    // and wrap slots (in bounds for every node; used only on the x or y wrap).
+    // BRANCH: the slots only when a node of the wave lies on either wrap,
+    // under one wave-uniform branch; the steps take it (loading the slots in
+    // every wave cost the 512^3 rock's FP16 step 4%, FP32 0.5%).  The adjoint
+    // loads them always: at one wave per SIMD the branch cost the 128^3
+    // pack's reverse step 8% (the 512^3 rock's 0.3%).
+    template <bool BRANCH = true>
     __device__ __forceinline__ void load(uint32_t, Pre c, Raw& r) const {
         const uint32_t x = c & ((1u << bx) - 1u);
         const uint32_t y = (c >> bx) & ((1u << by) - 1u);
@@ -381,15 +384,20 @@ struct BitmapIdx {
         r.a[0] = ent[em];
         r.a[1] = ent[e];
         r.a[2] = ent[ep];
-        unroll<3>([&](auto k) {
-            r.cn[decltype(k)::value] = 0u;
-            r.fb[decltype(k)::value] = 0;
-        });
-        if (__builtin_amdgcn_ballot_w64(x == 0u || x == nx - 1u || y == 0u || y == ny - 1u) != 0) {
+        auto slots = [&] {
             load12(counts + (z * ny + y), r.cn);
             uint32_t v[3];
             load12(wraps + ((z * 2u + (y == 0u ? 0u : 1u)) * R + x / kWordStep), v);
             unroll<3>([&](auto k) { r.fb[decltype(k)::value] = (int32_t)v[decltype(k)::value]; });
+        };
+        if constexpr (BRANCH) {
+            unroll<3>([&](auto k) {
+                r.cn[decltype(k)::value] = 0u;
+                r.fb[decltype(k)::value] = 0;
+            });
+            if (__builtin_amdgcn_ballot_w64(x == 0u || x == nx - 1u || y == 0u || y == ny - 1u) != 0) slots();
+        } else {
+            slots();
         }
     }
     // Calls put(I, row, which) for the 18 directions I of node c: the source
@@ -1167,13 +1175,13 @@ k_adjoint(const float* __restrict__ ain, float* __restrict__ aout, const float* 
         {
             const typename Ix::Pre p0 = ix.prefetch(n);
             typename Ix::Raw raw;
-            ix.load(n, p0, raw);
+            ix.template load<false>(n, p0, raw);
             ix.template offsets_adj<float, 19>(raw, p0, n, c, slack, of, ob);
         }
         for (;;) {
             __builtin_amdgcn_sched_barrier(0);
             typename Ix::Raw raw;
-            ix.load(n1, pre1, raw);
+            ix.template load<false>(n1, pre1, raw);
             __builtin_amdgcn_sched_barrier(0);
             // f: the forward's pulls; b: the transposed pulls
             const float* sb = chunk_base(st, c, slack);
