@@ -71,6 +71,16 @@ int main() {
         printf("512^3 fluid box: tile height %d\n", tz);
         if (tz != 32 || !fits(32) || fits(64)) ++bad;
     }
+    // ... and whose rows y -/+ 1 stay within the bitmap index's 18-bit base
+    // differences, (h + 1) nx + 1 < 2^17: 4095-voxel rows allow 16 planes,
+    // however small the span.
+    {
+        const int nx = 4095, ny = 3, nz = 200;
+        std::vector<uint8_t> g((size_t)nx * ny * nz, 0);
+        const int tz = node_tile_z(g.data(), nx, ny, nz);
+        printf("4095 x 3 x 200 fluid box: tile height %d\n", tz);
+        if (tz != 16) ++bad;
+    }
     printf("cases %d bad %d\n", cases, bad);
     return bad != 0;
 }
