@@ -75,8 +75,9 @@ constexpr int kChunk = 256;
 inline int64_t padded(int64_t nf) { return (nf + kChunk - 1) / kChunk * kChunk; }
 
 // Population layout in device memory: the kChunk nodes of chunk q = n / kChunk
-// keep their S values back to back (S = 19 populations, or 20 with a
-// reference-density slot), element (i, n) at q * S * kChunk + i * kChunk + n % kChunk.
+// keep their S values back to back (S = 19 populations; FP16 with a reference
+// keeps the references in a per-node array after the chunks), element (i, n)
+// at q * S * kChunk + i * kChunk + n % kChunk.
 inline int64_t state_elem(int i, int64_t n, int S = 19) {
     return (n / kChunk) * ((int64_t)S * kChunk) + (int64_t)i * kChunk + n % kChunk;
 }

@@ -15,7 +15,8 @@
 // written out as integer-coefficient adds on pair sums/differences of
 // opposite populations (no MFMA: at ~0.4 kflop per node-update against
 // ~150 bytes of traffic this is an HBM-bound stencil, not a contraction).
-// Storage holds deviations f_i - w_i rho0 (FP32, scaled FP16, BF16); all
+// Storage holds deviations f_i - w_i rho0 (FP32, scaled FP16, BF16, or FP16
+// relative to a per-node reference density); all
 // arithmetic is FP32; the mean-velocity reduction is FP64 and deterministic
 // (fixed per-block node ranges, fixed reduction trees).
 #include "lbm_kernels.hpp"
@@ -133,7 +134,8 @@ __device__ __forceinline__ void st_stream(T* base, uint32_t byte_off, T v) {
 // ------------------------------------------------------------------ layout
 // Element (i, m) of a population array sits at node_elem(m) + i * kThreads:
 // chunk q = m / 256 owns elements [q * S * 256, (q + 1) * S * 256), S = 19
-// values per node (20 with a reference-density slot).
+// values per node (FP16 with a reference keeps the references in a separate
+// per-node array after the chunks).
 constexpr uint32_t kChunkElems = 19u * kThreads;
 template <int S = 19>
 __device__ __forceinline__ uint32_t node_elem(uint32_t m) {
@@ -534,7 +536,7 @@ struct BitmapIdx {
     // starting at the even node (r0 - 1) & ~1 (4-byte aligned), holds them:
     // nine loads instead of nineteen.  Across the periodic x wrap (x = 0 or
     // nx - 1) the source at x -/+ 1 is the row's last / first node, outside the
-    // window; load_refs fetches those few separately.
+    // window; issue_refs fetches those few separately.
     struct RefPlan {
         uint32_t ro[9];  // byte offset of each row's window in the reference array
         uint64_t pos;    // bits 2i, 2i + 1: position of value i's source node in its row's window

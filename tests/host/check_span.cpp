@@ -24,7 +24,7 @@ int main() {
         ++cases;
         int64_t np = padded(nf);
         for (int tz : {node_tile_z(g.data(), nx, ny, nz), 1, 2, 3, 16})  // the image's height and fixed ones
-        for (int S : {19, 20}) {  // 19 populations, or 20 values with a reference-density slot
+        for (int S : {19, 20}) {  // 19 populations, and 20 values per node as a check of the layout's generality
             std::vector<int32_t> t((size_t)18 * np, -1);
             build_table(g.data(), nx, ny, nz, nf, np, t.data(), tz);
             auto st = row_starts(g.data(), nx, ny, nz, tz);

@@ -161,9 +161,9 @@ def test_workspace_query_counts_and_errors():
 
 
 def test_bitmap_row_length_limit():
-    """The bitmap's row records keep the row's fluid count in 12 bits: rows of
-    up to 4095 voxels are accepted, longer ones are refused (LBM_ERANGE) and
-    the table index takes them."""
+    """The bitmap index takes rows of up to 4095 voxels (its 18-bit row-base
+    differences and 16-bit count fields are sized for them); longer ones are
+    refused (LBM_ERANGE) and the table index takes them."""
     for nx, ok in ((4095, True), (4096, False)):
         m = np.zeros((1, 1, nx), np.uint8)
         if ok:
@@ -245,12 +245,13 @@ def test_gather_span_bounds_brute_force(tmp_path):
     assert "bad 0" in r.stdout
 
 
-def test_bitmap_records_decode_to_neighbour_table(tmp_path):
-    """The bitmap index (packed coordinate per node; per row word, the 8-byte
-    records of rows y - 1, y, y + 1 side by side) decodes, by the step
-    kernel's arithmetic modelled on the CPU, to exactly the pull sources of
-    the neighbour table on random periodic images, with every record load in
-    bounds, including row lengths around the 18-voxel word step."""
+def test_bitmap_entries_decode_to_neighbour_table(tmp_path):
+    """The bitmap index (packed coordinate per node; per row word and plane, a
+    16-byte entry with rows y - 1, y, y + 1, plus the x- and y-wrap slots)
+    decodes, by the step kernel's arithmetic modelled on the CPU, to exactly
+    the pull sources of the neighbour table on random periodic and mirrored
+    images, with every load in bounds, including row lengths around the
+    18-voxel word step."""
     import shutil
     import subprocess
     gxx = shutil.which("g++")
